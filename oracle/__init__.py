@@ -1,0 +1,26 @@
+"""CPU oracle for aggregation over dominated points.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()``
+and the CPU-baseline leg of ``bench.py``; never by the product package.
+
+It wraps the plain C of ``dom_agg_oracle.c`` (the paper's construction of
+Sec. 4 with the Sec. 5 improvement, its basic Sec. 4 variant and the plain
+definition of Sec. 1.2) and ``fenwick_pin.c`` (a textbook sweep used only to
+pin the construction for m = 2).  Arithmetic is fp64 for float weights and
+int64 for integer weights.
+"""
+from .oracle import (  # noqa: F401
+    OracleError,
+    brute,
+    construction,
+    construction_basic,
+    transposed_sum,
+    sscan,
+    prefix_set,
+    dense_rank,
+    bits_for,
+    fenwick2,
+    identity,
+    build,
+    lib_path,
+)
