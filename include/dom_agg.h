@@ -1,0 +1,209 @@
+/*
+ * dom_agg — aggregation over dominated points on one AMD Instinct MI355X
+ * (gfx950), computed by sorting, flat maps, segmented scans and zips as in
+ * Sroka & Tyszkiewicz, "Aggregating over Dominated Points by Sorting,
+ * Scanning, Zip and Flat Maps" (arXiv 2305.16751).
+ *
+ * The operation (Sec. 1.2 of the paper): data points D and queries Q in R^m,
+ * weights w on D, and an associative, commutative F with unit e.  For every
+ * query q the result is F over w(d) for all d in D with d < q in EVERY
+ * coordinate (strict dominance), or e when there is none.
+ *
+ * The computation (Sec. 4 with the improvement of Sec. 5):
+ *   plan     — coordinates only: per-axis dense ranks of axes 1..m-1 over D
+ *              and Q jointly, the order of all points along axis m (queries
+ *              before data on equal coordinates), the flat map of every point
+ *              into the prefix sets of its binary ranks (Lemma 2), and one
+ *              stable radix sort of the expanded records by bitstring tuple;
+ *   forward  — the segmented scan of the weights over the sorted records and
+ *              the regrouping of the partial aggregates by query;
+ *   backward — for F = sum only: the transposed dominance sum
+ *              grad_w[d] = sum of grad_out[q] over all q with d < q, as a
+ *              reverse segmented scan over the same sorted records.
+ *
+ * Conventions shared by every entry point:
+ *   - Device pointers: all coordinate, weight, output and gradient buffers
+ *     live in device memory of the current HIP device and are owned by the
+ *     caller.  Host pointers are marked (host) below.
+ *   - Streams: every call is ordered on the given hipStream_t (passed as
+ *     void*; NULL = the null stream).  dom_agg_plan blocks the host for a few
+ *     small device-to-host reads (sizes); forward and backward do not block
+ *     and allocate nothing, so they can be captured in a HIP graph.
+ *   - Errors: every call returns a status; nothing throws across the
+ *     boundary.  Arguments are validated before any HIP call is made.
+ *     dom_agg_last_error() returns a message for the last failure on the
+ *     calling thread.  A device fault is reported as DOM_AGG_EHIP by the
+ *     first call that observes it.
+ *   - Thread safety: a plan may be used by one thread at a time; distinct
+ *     plans are independent.
+ */
+#ifndef DOM_AGG_H
+#define DOM_AGG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DOM_AGG_OK = 0,
+    DOM_AGG_EINVAL = 1,       /* an argument is invalid */
+    DOM_AGG_ENAN = 2,         /* a coordinate is NaN (strict order undefined) */
+    DOM_AGG_ENOMEM = 3,       /* a workspace allocation failed */
+    DOM_AGG_ETOOBIG = 4,      /* > 2^32-1 expanded records, or sort keys wider than 64 bits */
+    DOM_AGG_EUNSUPPORTED = 5, /* op / dtype combination not provided */
+    DOM_AGG_ENODEV = 6,       /* no gfx950 device is current */
+    DOM_AGG_EHIP = 7          /* a HIP runtime call failed */
+} dom_agg_status;
+
+typedef enum {
+    DOM_AGG_SUM = 0,   /* e = 0 */
+    DOM_AGG_MAX = 1,   /* e = the weight dtype's minimum (-inf for floats) */
+    DOM_AGG_COUNT = 2  /* sum of unit weights; weights ignored (may be NULL) */
+} dom_agg_op;
+
+typedef enum {
+    DOM_AGG_I32 = 0,
+    DOM_AGG_I64 = 1,
+    DOM_AGG_F32 = 2,
+    DOM_AGG_F64 = 3
+} dom_agg_dtype;
+
+/* Plan flags. */
+enum {
+    /* Keep the sorted expanded records in the plan (default): forward and
+     * backward only scan them. */
+    DOM_AGG_KEEP = 0,
+    /* Keep only the per-point state (ranks, point order, record offsets);
+     * every forward/backward call rebuilds and re-sorts the expanded records
+     * in a temporary workspace and frees it afterwards.  For when memory is
+     * short.  Forward/backward then allocate, so they cannot be captured. */
+    DOM_AGG_RECOMPUTE = 2,
+    /* Capture forward/backward launches in a HIP graph on first use and
+     * replay it on later calls with the same arguments. */
+    DOM_AGG_GRAPH = 4,
+    /* Skip the autotuner and use the built-in tile and digit widths. */
+    DOM_AGG_NO_TUNE = 8
+};
+
+typedef struct dom_agg_plan_s *dom_agg_plan_t;
+
+typedef struct {
+    int64_t n_inst;        /* instances in the batch (1 for a plain call) */
+    int64_t n_data;        /* |D| over all instances */
+    int64_t n_query;       /* |Q| over all instances */
+    int64_t records;       /* E: expanded records (Sec. 5 flat map) */
+    int64_t data_records;  /* records that came from data points */
+    int32_t m;             /* dimension */
+    int32_t key_bits;      /* width of the record sort key */
+    int32_t L[4];          /* max over instances of ceil(log2 K_i), axes 1..m-1 */
+    int32_t sort_passes;   /* radix passes run by the record sort */
+    int32_t digit_bits;    /* radix digit width chosen for the record sort */
+    int32_t sort_tile;     /* records per workgroup tile in the record sort */
+    int32_t scan_tile;     /* records per workgroup tile in the segmented scans */
+    size_t workspace_bytes;/* device memory held by the plan */
+} dom_agg_plan_info;
+
+/*
+ * Device memory hook.  When set, every workspace allocation goes through
+ * alloc(bytes, stream, ctx) and is returned with release(ptr, stream, ctx)
+ * (e.g. PyTorch's caching allocator).  When unset, hipMalloc/hipFree are used.
+ * alloc returns NULL on failure (reported as DOM_AGG_ENOMEM).  Process-wide;
+ * pass NULLs to restore the default.  Not to be changed while plans exist.
+ */
+typedef void *(*dom_agg_alloc_fn)(size_t bytes, void *stream, void *ctx);
+typedef void (*dom_agg_release_fn)(void *ptr, void *stream, void *ctx);
+dom_agg_status dom_agg_set_allocator(dom_agg_alloc_fn alloc, dom_agg_release_fn release,
+                                     void *ctx);
+
+/*
+ * Build a plan from the coordinates (Sec. 4: union, ranks, binary ranks,
+ * flat map, sort; Sec. 5: the last axis stays real and orders each segment).
+ *
+ *   plan        (host) receives the new plan; unchanged on failure.
+ *   m           dimension, 1 <= m <= 4.
+ *   coord_dtype DOM_AGG_F32 or DOM_AGG_I32.  -0.0 and +0.0 are equal; NaN is
+ *               rejected with DOM_AGG_ENAN; +-inf order normally.
+ *   d_coords    device, [n_data, m] row-major, n_data = d_offsets[n_inst].
+ *   q_coords    device, [n_query, m] row-major, n_query = q_offsets[n_inst].
+ *               Either may be NULL when its count is 0.  Read only during
+ *               this call.
+ *   n_inst      number of independent instances, >= 1.
+ *   d_offsets   (host) [n_inst + 1] nondecreasing, d_offsets[0] = 0: instance
+ *               k owns data rows d_offsets[k] .. d_offsets[k+1]-1.
+ *   q_offsets   (host) likewise for queries.  Points of different instances
+ *               never interact.
+ *   flags       DOM_AGG_KEEP / DOM_AGG_RECOMPUTE | DOM_AGG_GRAPH | DOM_AGG_NO_TUNE.
+ *   stream      hipStream_t.
+ *
+ * Errors: EINVAL (m, counts, offsets, NULL pointers with nonzero counts,
+ * unknown flags or dtype), ENAN, ETOOBIG, ENOMEM, ENODEV, EHIP.
+ */
+dom_agg_status dom_agg_plan(dom_agg_plan_t *plan, int m, dom_agg_dtype coord_dtype,
+                            const void *d_coords, const void *q_coords, int64_t n_inst,
+                            const int64_t *d_offsets, const int64_t *q_offsets,
+                            uint32_t flags, void *stream);
+
+/*
+ * Forward (Sec. 4: segmented scan of the weights over the sorted records,
+ * then the regrouping by query ID).
+ *
+ *   op / weight_dtype   supported pairs and the output dtype:
+ *       SUM   I32 -> I64, I64 -> I64, F32 -> F32 (fp32 accumulation),
+ *             F64 -> F64
+ *       MAX   I32 -> I32, I64 -> I64, F32 -> F32, F64 -> F64
+ *       COUNT (weight_dtype ignored) -> I64
+ *   weights  device, [n_data] of weight_dtype in data-row order (NULL for COUNT).
+ *   out      device, [n_query] of the output dtype, fully overwritten.
+ *
+ * Integer results and MAX are exact and deterministic; fp32/fp64 sums are
+ * exact up to rounding order (the order of combination can differ between
+ * calls).
+ */
+dom_agg_status dom_agg_forward(dom_agg_plan_t plan, dom_agg_op op, dom_agg_dtype weight_dtype,
+                               const void *weights, void *out, void *stream);
+
+/*
+ * Backward of the SUM forward with respect to the weights: the transposed
+ * dominance sum grad_weights[d] = sum of grad_out[q] over all q with d < q.
+ * It reuses the plan's sorted records (or rebuilds them under
+ * DOM_AGG_RECOMPUTE) and scans them in reverse.
+ *
+ *   grad_dtype    DOM_AGG_F32 or DOM_AGG_F64 (of both buffers).
+ *   grad_out      device, [n_query].
+ *   grad_weights  device, [n_data], fully overwritten.
+ */
+dom_agg_status dom_agg_backward(dom_agg_plan_t plan, dom_agg_dtype grad_dtype,
+                                const void *grad_out, void *grad_weights, void *stream);
+
+/* Sizes of a plan.  info (host) is filled on success. */
+dom_agg_status dom_agg_plan_get_info(dom_agg_plan_t plan, dom_agg_plan_info *info);
+
+/* Releases the plan's device memory (stream-ordered on the plan's last
+ * stream) and the plan.  NULL is ignored. */
+void dom_agg_plan_destroy(dom_agg_plan_t plan);
+
+/* Static text for a status code. */
+const char *dom_agg_status_string(dom_agg_status status);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char *dom_agg_last_error(void);
+
+/*
+ * Per-kernel timing, for measurement.  While enabled (process-wide), every
+ * kernel the library launches is bracketed by a pair of HIP events recorded
+ * on the stream it runs on.  dom_agg_timing_read waits for the recorded
+ * events and writes, for up to `cap` distinct kernels, the kernel's name
+ * (host, static string), the summed milliseconds and the number of launches
+ * since the last dom_agg_timing_enable call; it returns the number of
+ * distinct kernels (or -1 on a HIP error).  Enabling resets the totals.
+ */
+dom_agg_status dom_agg_timing_enable(int enable);
+int dom_agg_timing_read(const char **names, double *total_ms, int64_t *launches, int cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DOM_AGG_H */

@@ -1,0 +1,1026 @@
+// C-ABI of the dominance aggregation library (declared in include/dom_agg.h).
+//
+// Host orchestration of the paper's construction (Sec. 4 with Sec. 5):
+//   plan:     per axis 1..m-1: order-preserving keys -> stable radix sort ->
+//             dense ranks; axis m: keys -> stable radix sort (the point order
+//             of Sec. 5); record counts and offsets; flat map; stable radix
+//             sort of the records by bitstring tuple.
+//   forward:  segmented scan of the weights + regrouping into out[query].
+//   backward: reverse segmented scan of grad_out + regrouping into grad[data].
+// Every step runs in the kernels of dominance.hpp, radix_sort.hpp and
+// seg_scan.hpp; this file only sizes, allocates, orders and checks.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <limits>
+#include <memory>
+#include <type_traits>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "dom_agg.h"
+#include "dominance.hpp"
+#include "seg_scan.hpp"
+#include "tuner.hpp"
+
+using namespace domagg;
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Errors: internal failures throw; every exported function catches.
+
+struct Failure {
+    dom_agg_status status;
+    std::string msg;
+};
+
+thread_local std::string t_last_error;
+
+[[noreturn]] void fail(dom_agg_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    throw Failure{st, buf};
+}
+
+#define HIPCHK(expr)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess) fail(DOM_AGG_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+template <class F>
+dom_agg_status guarded(F &&f) {
+    try {
+        f();
+        t_last_error.clear();
+        return DOM_AGG_OK;
+    } catch (const Failure &e) {
+        t_last_error = e.msg;
+        return e.status;
+    } catch (const std::bad_alloc &) {
+        t_last_error = "host allocation failed";
+        return DOM_AGG_ENOMEM;
+    } catch (...) {
+        t_last_error = "unexpected internal error";
+        return DOM_AGG_EHIP;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Device memory: through the registered hook, else hipMalloc/hipFree.
+
+dom_agg_alloc_fn g_alloc = nullptr;
+dom_agg_release_fn g_release = nullptr;
+void *g_alloc_ctx = nullptr;
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    hipStream_t stream = nullptr;
+
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept { *this = std::move(o); }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        if (this != &o) {
+            reset();
+            p = o.p;
+            bytes = o.bytes;
+            stream = o.stream;
+            o.p = nullptr;
+            o.bytes = 0;
+        }
+        return *this;
+    }
+    ~DevBuf() { reset(); }
+    void reset() {
+        if (p) {
+            if (g_release) g_release(p, stream, g_alloc_ctx);
+            else (void)hipFree(p);
+        }
+        p = nullptr;
+        bytes = 0;
+    }
+    void alloc(size_t b, hipStream_t s) {
+        reset();
+        if (b == 0) return;
+        stream = s;
+        void *q = nullptr;
+        if (g_alloc) {
+            q = g_alloc(b, (void *)s, g_alloc_ctx);
+        } else if (hipMalloc(&q, b) != hipSuccess) {
+            (void)hipGetLastError();
+            q = nullptr;
+        }
+        if (!q) fail(DOM_AGG_ENOMEM, "device allocation of %zu bytes failed", b);
+        p = q;
+        bytes = b;
+    }
+    template <class T>
+    T *as() const { return static_cast<T *>(p); }
+};
+
+// ---------------------------------------------------------------------------
+// Optional per-kernel event timing.
+
+struct TimedLaunch {
+    const char *name;
+    hipEvent_t a, b;
+};
+struct KernelTotal {
+    const char *name;
+    double ms;
+    int64_t launches;
+};
+
+std::mutex g_tmu;
+bool g_timing = false;
+std::vector<TimedLaunch> g_pending;
+std::vector<hipEvent_t> g_event_pool;
+std::vector<KernelTotal> g_totals;
+thread_local bool t_capturing = false;
+
+hipEvent_t take_event() {
+    if (!g_event_pool.empty()) {
+        hipEvent_t e = g_event_pool.back();
+        g_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    return e;
+}
+
+template <class F>
+void launch(const char *name, hipStream_t s, F &&f) {
+    bool timed;
+    {
+        std::lock_guard<std::mutex> lk(g_tmu);
+        timed = g_timing && !t_capturing;
+    }
+    if (!timed) {
+        f();
+        HIPCHK(hipGetLastError());
+        return;
+    }
+    hipEvent_t a, b;
+    {
+        std::lock_guard<std::mutex> lk(g_tmu);
+        a = take_event();
+        b = take_event();
+    }
+    HIPCHK(hipEventRecord(a, s));
+    f();
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(b, s));
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_pending.push_back({name, a, b});
+}
+
+// ---------------------------------------------------------------------------
+// Device check: the library is built for gfx950 only.
+
+void require_gfx950(int *device) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(DOM_AGG_ENODEV, "no HIP device is available");
+    }
+    static std::mutex mu;
+    static std::map<int, bool> ok;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = ok.find(dev);
+    if (it == ok.end()) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+            (void)hipGetLastError();
+            fail(DOM_AGG_ENODEV, "cannot query HIP device %d", dev);
+        }
+        it = ok.emplace(dev, std::strncmp(prop.gcnArchName, "gfx950", 6) == 0).first;
+    }
+    if (!it->second) fail(DOM_AGG_ENODEV, "device %d is not gfx950", dev);
+    *device = dev;
+}
+
+int bits_for(uint64_t K) {
+    int L = 0;
+    while (L < 63 && (1ull << L) < K) ++L;
+    return L;
+}
+
+uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+constexpr int kBlock = 256;
+constexpr uint64_t kMaxRecords = (1ull << 32) - (1ull << 20);
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// The plan.
+
+struct dom_agg_plan_s {
+    int device = 0;
+    int m = 0, nax = 0;
+    uint32_t flags = 0;
+    int64_t n_inst = 1, nD = 0, nQ = 0, n = 0;
+    bool batched = false;
+    int inst_bits = 0;
+    int Lmax[3] = {0, 0, 0};
+    int key_bits = 0;
+    bool key64 = false;
+    int field_shift[3] = {0, 0, 0};
+    int inst_shift = 0;
+    int64_t E = 0, E_D = 0;
+    std::vector<int> rec_shifts;  // radix passes the record sort runs
+    TuneChoice tune;
+
+    // per-point state, in last-axis order
+    DevBuf off, rs, pay, inst_s, ltab;
+    // sorted records (KEEP)
+    DevBuf rkeys, rvals;
+    // look-back words and ticket of the forward/backward scans
+    DevBuf scan_status, scan_ticket;
+    uint64_t scan_words = 0;
+    DevBuf ed_counter;
+
+    // graph replay cache
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    std::vector<uintptr_t> gkey;
+
+    size_t workspace() const {
+        return off.bytes + rs.bytes + pay.bytes + inst_s.bytes + ltab.bytes + rkeys.bytes +
+               rvals.bytes + scan_status.bytes + scan_ticket.bytes + ed_counter.bytes;
+    }
+};
+
+namespace {
+
+using Plan = dom_agg_plan_s;
+
+// small pinned host staging for the plan's size reads
+struct HostStage {
+    void *p = nullptr;
+    size_t bytes = 0;
+    ~HostStage() {
+        if (p) (void)hipHostFree(p);
+    }
+    void *get(size_t b) {
+        if (b > bytes) {
+            if (p) (void)hipHostFree(p);
+            p = nullptr;
+            HIPCHK(hipHostMalloc(&p, b, hipHostMallocDefault));
+            bytes = b;
+        }
+        return p;
+    }
+};
+
+template <class T>
+void fill(T *p, uint64_t n, T v, hipStream_t s) {
+    if (!n) return;
+    const unsigned grid = (unsigned)std::min<uint64_t>(ceil_div(n, kBlock), 4096);
+    launch("fill", s, [&] { fill_kernel<T><<<grid, kBlock, 0, s>>>(p, n, v); });
+}
+
+void clear_lookback(uint64_t *status, uint64_t words, uint32_t *ticket, hipStream_t s) {
+    const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(ceil_div(words, kBlock), 2048));
+    launch("clear_lookback", s,
+           [&] { clear_lookback_kernel<<<grid, kBlock, 0, s>>>(status, words, ticket); });
+}
+
+// ---------------------------------------------------------------------------
+// Radix sort driver.
+
+template <class K>
+const char *onesweep_name(int items) {
+    if constexpr (sizeof(K) == 4) return items == 8 ? "onesweep_u32_t2048" : "onesweep_u32_t4096";
+    else return items == 8 ? "onesweep_u64_t2048" : "onesweep_u64_t4096";
+}
+
+template <class K, int ITEMS>
+void onesweep_launch(const K *kin, const uint32_t *vin, K *kout, uint32_t *vout, uint32_t n,
+                     int shift, const uint32_t *bases, uint64_t *status, uint32_t *ticket,
+                     hipStream_t s) {
+    constexpr int TILE = kBlock * ITEMS;
+    const unsigned tiles = (unsigned)ceil_div(n, TILE);
+    clear_lookback(status, (uint64_t)tiles * kRadix, ticket, s);
+    launch(onesweep_name<K>(ITEMS), s, [&] {
+        onesweep_kernel<K, kBlock, ITEMS><<<tiles, kBlock, 0, s>>>(kin, vin, kout, vout, n, shift,
+                                                                   bases, status, ticket);
+    });
+}
+
+// Sorts (kA, vA) by the listed digit shifts; returns true when the result
+// ended up in (kB, vB).  bases: [passes][256] (pass p at shift 8p).
+template <class K>
+bool radix_sort(K *kA, uint32_t *vA, K *kB, uint32_t *vB, uint64_t n, const std::vector<int> &shifts,
+                const uint32_t *bases, int items, hipStream_t s) {
+    if (n == 0 || shifts.empty()) return false;
+    const int tile = kBlock * (items == 8 ? 8 : 16);
+    DevBuf status, ticket;
+    status.alloc(ceil_div(n, tile) * kRadix * sizeof(uint64_t), s);
+    ticket.alloc(sizeof(uint32_t) * 4, s);
+    bool inB = false;
+    for (int sh : shifts) {
+        const K *ki = inB ? kB : kA;
+        const uint32_t *vi = inB ? vB : vA;
+        K *ko = inB ? kA : kB;
+        uint32_t *vo = inB ? vA : vB;
+        const uint32_t *b = bases + (sh / kRadixBits) * kRadix;
+        if (items == 8)
+            onesweep_launch<K, 8>(ki, vi, ko, vo, (uint32_t)n, sh, b, status.as<uint64_t>(),
+                                  ticket.as<uint32_t>(), s);
+        else
+            onesweep_launch<K, 16>(ki, vi, ko, vo, (uint32_t)n, sh, b, status.as<uint64_t>(),
+                                   ticket.as<uint32_t>(), s);
+        inB = !inB;
+    }
+    // status/ticket are released stream-ordered (or by hipFree, which waits)
+    return inB;
+}
+
+// Passes whose digit is not the same for every key.
+std::vector<int> live_shifts(const uint32_t *counts, int passes, uint64_t n) {
+    std::vector<int> sh;
+    for (int p = 0; p < passes; ++p) {
+        bool trivial = false;
+        for (int d = 0; d < kRadix; ++d)
+            if (counts[p * kRadix + d] == n) trivial = true;
+        if (!trivial) sh.push_back(p * kRadixBits);
+    }
+    return sh;
+}
+
+// ---------------------------------------------------------------------------
+// Scan driver.
+
+template <class Prob, int ITEMS>
+void scan_launch(const char *name, const Prob &p, uint64_t n, uint64_t *status, uint64_t words_cap,
+                 uint32_t *ticket, hipStream_t s) {
+    if (n == 0) return;
+    constexpr int TILE = kBlock * ITEMS;
+    const uint64_t tiles = ceil_div(n, TILE);
+    const uint64_t words = tiles * ScanStatusWords<typename Prob::V>::kWords;
+    if (words > words_cap) fail(DOM_AGG_EHIP, "internal: scan status too small");
+    clear_lookback(status, words, ticket, s);
+    launch(name, s, [&] {
+        seg_scan_kernel<Prob, kBlock, ITEMS><<<(unsigned)tiles, kBlock, 0, s>>>(p, n, status, ticket);
+    });
+}
+
+// ---------------------------------------------------------------------------
+// Plan construction, per-point part.
+
+template <class C, class KP>
+void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const int64_t *qoff,
+                  hipStream_t s, HostStage &hs, DevBuf &sig_keys, DevBuf &sig_slots) {
+    const uint32_t n = (uint32_t)P->n, nQ = (uint32_t)P->nQ;
+    const int m = P->m, nax = P->nax;
+    const int64_t ni = P->n_inst;
+
+    DevBuf inst_of_slot, doff_dev, qoff_dev;
+    if (P->batched) {
+        doff_dev.alloc((ni + 1) * sizeof(int64_t), s);
+        qoff_dev.alloc((ni + 1) * sizeof(int64_t), s);
+        HIPCHK(hipMemcpyAsync(doff_dev.p, doff, (ni + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(qoff_dev.p, qoff, (ni + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        inst_of_slot.alloc((size_t)n * sizeof(uint32_t), s);
+        launch("instance_of_slot", s, [&] {
+            instance_of_slot_kernel<<<(unsigned)ceil_div(n, kBlock), kBlock, 0, s>>>(
+                qoff_dev.as<int64_t>(), doff_dev.as<int64_t>(), ni, nQ, n, inst_of_slot.as<uint32_t>());
+        });
+    }
+
+    DevBuf kA, kB, vA, vB, rank, kcount, nanflag, part, counts, bases;
+    kA.alloc((size_t)n * sizeof(KP), s);
+    kB.alloc((size_t)n * sizeof(KP), s);
+    vA.alloc((size_t)n * 4, s);
+    vB.alloc((size_t)n * 4, s);
+    if (nax) {
+        rank.alloc((size_t)nax * n * 4, s);
+        kcount.alloc((size_t)nax * ni * 4, s);
+        fill(kcount.as<uint32_t>(), (uint64_t)nax * ni, 0u, s);
+    }
+    nanflag.alloc(4, s);
+    fill(nanflag.as<uint32_t>(), 1, 0u, s);
+
+    const int key_bits = 32 + (P->batched ? P->inst_bits : 0);
+    const int passes = (int)ceil_div(key_bits, kRadixBits);
+    const unsigned ext_blocks = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(ceil_div(n, kBlock), 1024));
+    part.alloc((size_t)ext_blocks * passes * kRadix * 4, s);
+    counts.alloc((size_t)passes * kRadix * 4, s);
+    bases.alloc((size_t)passes * kRadix * 4, s);
+
+    DevBuf scan_status, scan_ticket;
+    scan_status.alloc((ceil_div(n, kBlock * 8) + 1) * sizeof(uint64_t) * 2, s);
+    scan_ticket.alloc(16, s);
+
+    // expanded axes first, the real (last) axis last
+    for (int axis = 0; axis < m; ++axis) {
+        launch("extract_keys", s, [&] {
+            extract_keys_kernel<KP, C, kBlock><<<ext_blocks, kBlock, 0, s>>>(
+                qq, dq, m, axis, nQ, n, inst_of_slot.as<uint32_t>(), kA.as<KP>(), vA.as<uint32_t>(),
+                passes, part.as<uint32_t>(), nanflag.as<uint32_t>());
+        });
+        launch("hist_reduce", s, [&] {
+            hist_reduce_kernel<<<passes, kRadix, 0, s>>>(part.as<uint32_t>(), (int)ext_blocks, passes,
+                                                         counts.as<uint32_t>(), bases.as<uint32_t>());
+        });
+        const size_t cb = (size_t)passes * kRadix * 4;
+        uint32_t *h = static_cast<uint32_t *>(hs.get(cb + 4));
+        HIPCHK(hipMemcpyAsync(h, counts.p, cb, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(h + passes * kRadix, nanflag.p, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (h[passes * kRadix]) fail(DOM_AGG_ENAN, "a coordinate on axis %d is NaN", axis);
+        const std::vector<int> shifts = live_shifts(h, passes, n);
+        const bool inB = radix_sort<KP>(kA.as<KP>(), vA.as<uint32_t>(), kB.as<KP>(), vB.as<uint32_t>(), n,
+                                        shifts, bases.as<uint32_t>(), P->tune.point_sort_items, s);
+        DevBuf &sk = inB ? kB : kA;
+        DevBuf &sv = inB ? vB : vA;
+        if (axis < nax) {
+            RankProblem<KP> rp{sk.as<KP>(), sv.as<uint32_t>(), rank.as<uint32_t>() + (size_t)axis * n,
+                               kcount.as<uint32_t>() + (size_t)axis * ni};
+            scan_launch<RankProblem<KP>, sizeof(KP) == 4 ? 16 : 8>(
+                "rank_scan", rp, n, scan_status.as<uint64_t>(), scan_status.bytes / 8,
+                scan_ticket.as<uint32_t>(), s);
+        } else {
+            sig_keys = std::move(sk);
+            sig_slots = std::move(sv);
+        }
+    }
+
+    // Bit widths per instance and axis (ceil(log2 K)), and the record key layout.
+    std::vector<uint8_t> lt((size_t)nax * ni, 0);
+    if (nax) {
+        uint32_t *h = static_cast<uint32_t *>(hs.get((size_t)nax * ni * 4));
+        HIPCHK(hipMemcpyAsync(h, kcount.p, (size_t)nax * ni * 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int a = 0; a < nax; ++a) {
+            int lm = 0;
+            for (int64_t k = 0; k < ni; ++k) {
+                const int L = bits_for(h[(size_t)a * ni + k]);
+                lt[(size_t)a * ni + k] = (uint8_t)L;
+                lm = std::max(lm, L);
+            }
+            P->Lmax[a] = lm;
+        }
+    }
+    int sum = 0;
+    for (int a = nax - 1; a >= 0; --a) {
+        P->field_shift[a] = sum;
+        sum += P->Lmax[a];
+    }
+    P->inst_shift = P->batched ? sum : 0;
+    P->key_bits = sum + (P->batched ? P->inst_bits : 0);
+    if (P->key_bits > 64) fail(DOM_AGG_ETOOBIG, "record sort key needs %d bits (> 64)", P->key_bits);
+    P->key64 = P->key_bits > 32;
+
+    if (nax) {
+        P->ltab.alloc(lt.size(), s);
+        HIPCHK(hipMemcpyAsync(P->ltab.p, lt.data(), lt.size(), hipMemcpyHostToDevice, s));
+        P->rs.alloc((size_t)nax * n * 4, s);
+    }
+    P->off.alloc(((size_t)n + 1) * 8, s);
+    P->pay.alloc((size_t)n * 4, s);
+    if (P->batched) P->inst_s.alloc((size_t)n * 4, s);
+
+    auto count = [&](auto nax_c) {
+        constexpr int NAX = decltype(nax_c)::value;
+        CountProblem<KP, NAX> cp{sig_keys.as<KP>(), sig_slots.as<uint32_t>(), rank.as<uint32_t>(),
+                                 P->ltab.as<uint8_t>(), (uint32_t)ni, nQ, n,
+                                 P->off.as<uint64_t>(), P->rs.as<uint32_t>(), P->pay.as<uint32_t>(),
+                                 P->inst_s.as<uint32_t>()};
+        scan_launch<CountProblem<KP, NAX>, sizeof(KP) == 4 ? 16 : 8>(
+            "count_scan", cp, n, scan_status.as<uint64_t>(), scan_status.bytes / 8,
+            scan_ticket.as<uint32_t>(), s);
+    };
+    switch (nax) {
+        case 0: count(std::integral_constant<int, 0>{}); break;
+        case 1: count(std::integral_constant<int, 1>{}); break;
+        case 2: count(std::integral_constant<int, 2>{}); break;
+        default: count(std::integral_constant<int, 3>{}); break;
+    }
+    uint64_t *h = static_cast<uint64_t *>(hs.get(8));
+    HIPCHK(hipMemcpyAsync(h, P->off.as<uint64_t>() + n, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    P->E = (int64_t)*h;
+    if ((uint64_t)P->E > kMaxRecords)
+        fail(DOM_AGG_ETOOBIG, "flat map yields %lld records (limit %llu)", (long long)P->E,
+             (unsigned long long)kMaxRecords);
+}
+
+// ---------------------------------------------------------------------------
+// The flat map and the record sort.  With `probe`, the histogram is read back
+// to find the live radix passes (stored in the plan); otherwise the stored
+// passes are used with no host synchronisation before the sort.
+
+template <class K>
+void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &outK, DevBuf &outV) {
+    const uint64_t E = (uint64_t)P->E;
+    DevBuf kA, kB, vA, vB, part, counts, bases;
+    kA.alloc(E * sizeof(K), s);
+    vA.alloc(E * 4, s);
+    const int passes = std::max(1, (int)ceil_div(P->key_bits, kRadixBits));
+    constexpr int EITEMS = 16;
+    constexpr int CHUNK = kBlock * EITEMS;
+    const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(ceil_div(E, CHUNK), 2048));
+    part.alloc((size_t)grid * passes * kRadix * 4, s);
+    counts.alloc((size_t)passes * kRadix * 4, s);
+    bases.alloc((size_t)passes * kRadix * 4, s);
+    if (!P->ed_counter.p) P->ed_counter.alloc(8, s);
+    fill(P->ed_counter.as<unsigned long long>(), 1, 0ull, s);
+
+    EmitArgs a{};
+    a.off = P->off.as<uint64_t>();
+    a.rs = P->rs.as<uint32_t>();
+    a.pay = P->pay.as<uint32_t>();
+    a.inst_s = P->inst_s.as<uint32_t>();
+    a.ltab = P->ltab.as<uint8_t>();
+    a.n = (uint32_t)P->n;
+    a.n_inst = (uint32_t)P->n_inst;
+    a.E = E;
+    for (int i = 0; i < 3; ++i) a.field_shift[i] = P->field_shift[i];
+    a.inst_shift = P->inst_shift;
+    a.passes = passes;
+    a.hist_part = part.as<uint32_t>();
+    a.data_records = P->ed_counter.as<unsigned long long>();
+    auto emit = [&](auto nax_c) {
+        constexpr int NAX = decltype(nax_c)::value;
+        launch("flatmap_emit", s, [&] {
+            emit_kernel<K, NAX, kBlock, EITEMS><<<grid, kBlock, 0, s>>>(a, kA.as<K>(), vA.as<uint32_t>());
+        });
+    };
+    switch (P->nax) {
+        case 0: emit(std::integral_constant<int, 0>{}); break;
+        case 1: emit(std::integral_constant<int, 1>{}); break;
+        case 2: emit(std::integral_constant<int, 2>{}); break;
+        default: emit(std::integral_constant<int, 3>{}); break;
+    }
+    launch("hist_reduce", s, [&] {
+        hist_reduce_kernel<<<passes, kRadix, 0, s>>>(part.as<uint32_t>(), (int)grid, passes,
+                                                     counts.as<uint32_t>(), bases.as<uint32_t>());
+    });
+    if (probe) {
+        const size_t cb = (size_t)passes * kRadix * 4;
+        uint32_t *h = static_cast<uint32_t *>(hs->get(cb + 8));
+        HIPCHK(hipMemcpyAsync(h, counts.p, cb, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(h + passes * kRadix, P->ed_counter.p, 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        P->rec_shifts = P->key_bits ? live_shifts(h, passes, E) : std::vector<int>{};
+        uint64_t ed;
+        std::memcpy(&ed, h + passes * kRadix, 8);
+        P->E_D = (int64_t)ed;
+    }
+    bool inB = false;
+    if (!P->rec_shifts.empty()) {
+        kB.alloc(E * sizeof(K), s);
+        vB.alloc(E * 4, s);
+        inB = radix_sort<K>(kA.as<K>(), vA.as<uint32_t>(), kB.as<K>(), vB.as<uint32_t>(), E, P->rec_shifts,
+                            bases.as<uint32_t>(), P->tune.record_sort_items, s);
+    }
+    outK = std::move(inB ? kB : kA);
+    outV = std::move(inB ? vB : vA);
+}
+
+void records_for_call(Plan *P, hipStream_t s, DevBuf &k, DevBuf &v, const void **kp, const uint32_t **vp) {
+    if (P->flags & DOM_AGG_RECOMPUTE) {
+        if (P->key64) build_records<uint64_t>(P, s, nullptr, false, k, v);
+        else build_records<uint32_t>(P, s, nullptr, false, k, v);
+        *kp = k.p;
+        *vp = v.as<uint32_t>();
+    } else {
+        *kp = P->rkeys.p;
+        *vp = P->rvals.as<uint32_t>();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Forward and backward.
+
+template <class K, class W, class V, int OP>
+void forward_typed(Plan *P, const void *kp, const uint32_t *vp, const void *w, void *out, hipStream_t s) {
+    ForwardProblem<K, W, V, OP> fp{static_cast<const K *>(kp), vp, static_cast<const W *>(w),
+                                   static_cast<V *>(out)};
+    V e;
+    if constexpr (OP == OP_MAX) {
+        if constexpr (std::is_floating_point<V>::value) e = -std::numeric_limits<V>::infinity();
+        else e = std::numeric_limits<V>::min();
+    } else {
+        e = V(0);
+    }
+    fill(static_cast<V *>(out), (uint64_t)P->nQ, e, s);
+    if (P->tune.scan_items == 8 || sizeof(K) == 8)
+        scan_launch<ForwardProblem<K, W, V, OP>, 8>("forward_scan", fp, (uint64_t)P->E,
+                                                    P->scan_status.as<uint64_t>(), P->scan_words,
+                                                    P->scan_ticket.as<uint32_t>(), s);
+    else
+        scan_launch<ForwardProblem<K, W, V, OP>, 16>("forward_scan", fp, (uint64_t)P->E,
+                                                     P->scan_status.as<uint64_t>(), P->scan_words,
+                                                     P->scan_ticket.as<uint32_t>(), s);
+}
+
+template <class K>
+void forward_dispatch(Plan *P, dom_agg_op op, dom_agg_dtype wdt, const void *kp, const uint32_t *vp,
+                      const void *w, void *out, hipStream_t s) {
+    if (op == DOM_AGG_COUNT) return forward_typed<K, uint8_t, int64_t, OP_COUNT>(P, kp, vp, w, out, s);
+    if (op == DOM_AGG_SUM) {
+        switch (wdt) {
+            case DOM_AGG_I32: return forward_typed<K, int32_t, int64_t, OP_SUM>(P, kp, vp, w, out, s);
+            case DOM_AGG_I64: return forward_typed<K, int64_t, int64_t, OP_SUM>(P, kp, vp, w, out, s);
+            case DOM_AGG_F32: return forward_typed<K, float, float, OP_SUM>(P, kp, vp, w, out, s);
+            case DOM_AGG_F64: return forward_typed<K, double, double, OP_SUM>(P, kp, vp, w, out, s);
+        }
+    } else {
+        switch (wdt) {
+            case DOM_AGG_I32: return forward_typed<K, int32_t, int32_t, OP_MAX>(P, kp, vp, w, out, s);
+            case DOM_AGG_I64: return forward_typed<K, int64_t, int64_t, OP_MAX>(P, kp, vp, w, out, s);
+            case DOM_AGG_F32: return forward_typed<K, float, float, OP_MAX>(P, kp, vp, w, out, s);
+            case DOM_AGG_F64: return forward_typed<K, double, double, OP_MAX>(P, kp, vp, w, out, s);
+        }
+    }
+}
+
+template <class K, class G>
+void backward_typed(Plan *P, const void *kp, const uint32_t *vp, const void *g, void *grad, hipStream_t s) {
+    BackwardProblem<K, G> bp{static_cast<const K *>(kp), vp, static_cast<const G *>(g), static_cast<G *>(grad),
+                             (uint64_t)P->E};
+    fill(static_cast<G *>(grad), (uint64_t)P->nD, G(0), s);
+    if (P->tune.scan_items == 8 || sizeof(K) == 8)
+        scan_launch<BackwardProblem<K, G>, 8>("backward_scan", bp, (uint64_t)P->E, P->scan_status.as<uint64_t>(),
+                                              P->scan_words, P->scan_ticket.as<uint32_t>(), s);
+    else
+        scan_launch<BackwardProblem<K, G>, 16>("backward_scan", bp, (uint64_t)P->E, P->scan_status.as<uint64_t>(),
+                                               P->scan_words, P->scan_ticket.as<uint32_t>(), s);
+}
+
+// Runs `body` directly, or through the plan's HIP graph in DOM_AGG_GRAPH mode.
+template <class F>
+void maybe_graph(Plan *P, const std::vector<uintptr_t> &key, hipStream_t s, F &&body) {
+    if (!(P->flags & DOM_AGG_GRAPH) || (P->flags & DOM_AGG_RECOMPUTE)) {
+        body(s);
+        return;
+    }
+    if (!P->gexec || P->gkey != key) {
+        if (P->gexec) {
+            (void)hipGraphExecDestroy(P->gexec);
+            P->gexec = nullptr;
+        }
+        if (!P->cap_stream) HIPCHK(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
+        t_capturing = true;
+        try {
+            body(P->cap_stream);
+        } catch (...) {
+            t_capturing = false;
+            hipGraph_t junk = nullptr;
+            (void)hipStreamEndCapture(P->cap_stream, &junk);
+            if (junk) (void)hipGraphDestroy(junk);
+            throw;
+        }
+        t_capturing = false;
+        HIPCHK(hipStreamEndCapture(P->cap_stream, &g));
+        hipGraphExec_t ex = nullptr;
+        const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        HIPCHK(e);
+        P->gexec = ex;
+        P->gkey = key;
+    }
+    launch("graph_replay", s, [&] { HIPCHK(hipGraphLaunch(P->gexec, s)); });
+}
+
+
+// ---------------------------------------------------------------------------
+// Autotuner: times the record sort (flat map + radix passes) and the forward
+// scan for each tile candidate on the plan's own records and keeps the
+// fastest.  Results are cached per (m, key bits, ceil(log2 E)).  The sorted
+// records do not depend on the tile, so the plan's records are kept as built.
+
+float time_ms(hipStream_t s, const std::function<void()> &f) {
+    hipEvent_t a, b;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    HIPCHK(hipEventRecord(a, s));
+    f();
+    HIPCHK(hipEventRecord(b, s));
+    HIPCHK(hipEventSynchronize(b));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return ms;
+}
+
+void tune_plan(Plan *P, hipStream_t s) {
+    TuneCache &tc = TuneCache::get();
+    if (!tc.enabled() || P->E <= 0) return;
+    const TuneKey key{P->m, P->key_bits, bits_for((uint64_t)P->E)};
+    TuneChoice c;
+    if (tc.lookup(key, &c)) {
+        P->tune.record_sort_items = c.record_sort_items;
+        P->tune.scan_items = c.scan_items;
+        return;
+    }
+    // the per-point state is still present here (plan construction)
+    float best = 1e30f;
+    int best_items = P->tune.record_sort_items;
+    for (int items : {8, 16}) {
+        P->tune.record_sort_items = items;
+        DevBuf k, v;
+        const float ms = time_ms(s, [&] {
+            if (P->key64) build_records<uint64_t>(P, s, nullptr, false, k, v);
+            else build_records<uint32_t>(P, s, nullptr, false, k, v);
+        });
+        if (ms < best) {
+            best = ms;
+            best_items = items;
+        }
+    }
+    P->tune.record_sort_items = best_items;
+    if (!P->key64 && P->rkeys.p && P->nQ > 0) {
+        DevBuf out;
+        out.alloc((size_t)P->nQ * 8, s);
+        best = 1e30f;
+        int best_scan = P->tune.scan_items;
+        for (int items : {8, 16}) {
+            P->tune.scan_items = items;
+            forward_dispatch<uint32_t>(P, DOM_AGG_COUNT, DOM_AGG_I64, P->rkeys.p, P->rvals.as<uint32_t>(),
+                                       nullptr, out.p, s);  // warm
+            const float ms = time_ms(s, [&] {
+                forward_dispatch<uint32_t>(P, DOM_AGG_COUNT, DOM_AGG_I64, P->rkeys.p, P->rvals.as<uint32_t>(),
+                                           nullptr, out.p, s);
+            });
+            if (ms < best) {
+                best = ms;
+                best_scan = items;
+            }
+        }
+        P->tune.scan_items = best_scan;
+    }
+    tc.store(key, P->tune);
+}
+
+}  // namespace
+
+// ===========================================================================
+// Exported entry points.
+
+extern "C" {
+
+const char *dom_agg_status_string(dom_agg_status st) {
+    switch (st) {
+        case DOM_AGG_OK: return "ok";
+        case DOM_AGG_EINVAL: return "invalid argument";
+        case DOM_AGG_ENAN: return "NaN coordinate";
+        case DOM_AGG_ENOMEM: return "out of device memory";
+        case DOM_AGG_ETOOBIG: return "problem too large";
+        case DOM_AGG_EUNSUPPORTED: return "unsupported op or dtype";
+        case DOM_AGG_ENODEV: return "no gfx950 device";
+        case DOM_AGG_EHIP: return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+const char *dom_agg_last_error(void) { return t_last_error.c_str(); }
+
+dom_agg_status dom_agg_set_allocator(dom_agg_alloc_fn alloc, dom_agg_release_fn release, void *ctx) {
+    return guarded([&] {
+        if ((alloc == nullptr) != (release == nullptr))
+            fail(DOM_AGG_EINVAL, "alloc and release must both be set or both be NULL");
+        g_alloc = alloc;
+        g_release = release;
+        g_alloc_ctx = ctx;
+    });
+}
+
+dom_agg_status dom_agg_plan(dom_agg_plan_t *plan, int m, dom_agg_dtype coord_dtype, const void *d_coords,
+                            const void *q_coords, int64_t n_inst, const int64_t *d_offsets,
+                            const int64_t *q_offsets, uint32_t flags, void *stream) {
+    return guarded([&] {
+        // ---- validation: no HIP call before this block completes ----
+        if (!plan) fail(DOM_AGG_EINVAL, "plan is NULL");
+        if (m < 1 || m > 4) fail(DOM_AGG_EINVAL, "m = %d is outside [1, 4]", m);
+        if (coord_dtype == DOM_AGG_F64 || coord_dtype == DOM_AGG_I64)
+            fail(DOM_AGG_EUNSUPPORTED, "coordinates must be float32 or int32");
+        if (coord_dtype != DOM_AGG_F32 && coord_dtype != DOM_AGG_I32)
+            fail(DOM_AGG_EINVAL, "unknown coordinate dtype %d", (int)coord_dtype);
+        if (n_inst < 1 || n_inst > (1ll << 30)) fail(DOM_AGG_EINVAL, "n_inst = %lld", (long long)n_inst);
+        if (!d_offsets || !q_offsets) fail(DOM_AGG_EINVAL, "offsets are NULL");
+        if (d_offsets[0] != 0 || q_offsets[0] != 0) fail(DOM_AGG_EINVAL, "offsets must start at 0");
+        for (int64_t k = 0; k < n_inst; ++k)
+            if (d_offsets[k + 1] < d_offsets[k] || q_offsets[k + 1] < q_offsets[k])
+                fail(DOM_AGG_EINVAL, "offsets decrease at instance %lld", (long long)k);
+        const int64_t nD = d_offsets[n_inst], nQ = q_offsets[n_inst];
+        if (nD > 0 && !d_coords) fail(DOM_AGG_EINVAL, "d_coords is NULL with %lld data points", (long long)nD);
+        if (nQ > 0 && !q_coords) fail(DOM_AGG_EINVAL, "q_coords is NULL with %lld queries", (long long)nQ);
+        if (nD + nQ > 0x7fffffffll) fail(DOM_AGG_ETOOBIG, "|D| + |Q| must be below 2^31");
+        if (flags & ~(uint32_t)(DOM_AGG_RECOMPUTE | DOM_AGG_GRAPH | DOM_AGG_NO_TUNE))
+            fail(DOM_AGG_EINVAL, "unknown flags 0x%x", flags);
+        // ---- device work ----
+        int dev;
+        require_gfx950(&dev);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        auto P = std::make_unique<Plan>();
+        P->device = dev;
+        P->m = m;
+        P->nax = m - 1;
+        P->flags = flags;
+        P->n_inst = n_inst;
+        P->nD = nD;
+        P->nQ = nQ;
+        P->n = nD + nQ;
+        P->batched = n_inst > 1;
+        P->inst_bits = P->batched ? bits_for((uint64_t)n_inst) : 0;
+        P->tune = default_tune();
+        if (P->n > 0) {
+            HostStage hs;
+            DevBuf sig_keys, sig_slots;
+            if (coord_dtype == DOM_AGG_F32) {
+                if (P->batched)
+                    build_points<float, uint64_t>(P.get(), (const float *)d_coords, (const float *)q_coords,
+                                                  d_offsets, q_offsets, s, hs, sig_keys, sig_slots);
+                else
+                    build_points<float, uint32_t>(P.get(), (const float *)d_coords, (const float *)q_coords,
+                                                  d_offsets, q_offsets, s, hs, sig_keys, sig_slots);
+            } else {
+                if (P->batched)
+                    build_points<int32_t, uint64_t>(P.get(), (const int32_t *)d_coords, (const int32_t *)q_coords,
+                                                    d_offsets, q_offsets, s, hs, sig_keys, sig_slots);
+                else
+                    build_points<int32_t, uint32_t>(P.get(), (const int32_t *)d_coords,
+                                                    (const int32_t *)q_coords, d_offsets, q_offsets, s, hs,
+                                                    sig_keys, sig_slots);
+            }
+            sig_keys.reset();
+            sig_slots.reset();
+            const uint64_t tiles = ceil_div((uint64_t)std::max<int64_t>(P->E, 1), kBlock * 8);
+            P->scan_words = tiles * 2;
+            P->scan_status.alloc(P->scan_words * 8, s);
+            P->scan_ticket.alloc(16, s);
+            if (P->E > 0) {
+                DevBuf k, v;
+                if (P->key64) build_records<uint64_t>(P.get(), s, &hs, true, k, v);
+                else build_records<uint32_t>(P.get(), s, &hs, true, k, v);
+                P->rkeys = std::move(k);
+                P->rvals = std::move(v);
+                if (!(flags & DOM_AGG_NO_TUNE)) tune_plan(P.get(), s);
+                if (flags & DOM_AGG_RECOMPUTE) {
+                    P->rkeys.reset();
+                    P->rvals.reset();
+                } else {
+                    // the per-point state is only needed to rebuild the records
+                    P->rs.reset();
+                    P->pay.reset();
+                    P->inst_s.reset();
+                    P->off.reset();
+                    P->ltab.reset();
+                }
+            }
+            HIPCHK(hipStreamSynchronize(s));
+        }
+        *plan = P.release();
+    });
+}
+
+dom_agg_status dom_agg_forward(dom_agg_plan_t plan, dom_agg_op op, dom_agg_dtype weight_dtype,
+                               const void *weights, void *out, void *stream) {
+    return guarded([&] {
+        if (!plan) fail(DOM_AGG_EINVAL, "plan is NULL");
+        if (op != DOM_AGG_SUM && op != DOM_AGG_MAX && op != DOM_AGG_COUNT)
+            fail(DOM_AGG_EINVAL, "unknown op %d", (int)op);
+        if (op != DOM_AGG_COUNT && (weight_dtype < DOM_AGG_I32 || weight_dtype > DOM_AGG_F64))
+            fail(DOM_AGG_EINVAL, "unknown weight dtype %d", (int)weight_dtype);
+        if (op != DOM_AGG_COUNT && plan->nD > 0 && !weights) fail(DOM_AGG_EINVAL, "weights are NULL");
+        if (plan->nQ > 0 && !out) fail(DOM_AGG_EINVAL, "out is NULL");
+        if (plan->nQ == 0) return;
+        int dev;
+        require_gfx950(&dev);
+        if (dev != plan->device) fail(DOM_AGG_EINVAL, "plan belongs to device %d, current is %d", plan->device, dev);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const std::vector<uintptr_t> key{1, (uintptr_t)op, (uintptr_t)weight_dtype, (uintptr_t)weights,
+                                         (uintptr_t)out};
+        maybe_graph(plan, key, s, [&](hipStream_t cs) {
+            DevBuf k, v;
+            const void *kp = nullptr;
+            const uint32_t *vp = nullptr;
+            if (plan->E > 0) records_for_call(plan, cs, k, v, &kp, &vp);
+            if (plan->key64) forward_dispatch<uint64_t>(plan, op, weight_dtype, kp, vp, weights, out, cs);
+            else forward_dispatch<uint32_t>(plan, op, weight_dtype, kp, vp, weights, out, cs);
+        });
+    });
+}
+
+dom_agg_status dom_agg_backward(dom_agg_plan_t plan, dom_agg_dtype grad_dtype, const void *grad_out,
+                                void *grad_weights, void *stream) {
+    return guarded([&] {
+        if (!plan) fail(DOM_AGG_EINVAL, "plan is NULL");
+        if (grad_dtype == DOM_AGG_I32 || grad_dtype == DOM_AGG_I64)
+            fail(DOM_AGG_EUNSUPPORTED, "the gradient is provided for float32 and float64 only");
+        if (grad_dtype != DOM_AGG_F32 && grad_dtype != DOM_AGG_F64)
+            fail(DOM_AGG_EINVAL, "unknown gradient dtype %d", (int)grad_dtype);
+        if (plan->nQ > 0 && !grad_out) fail(DOM_AGG_EINVAL, "grad_out is NULL");
+        if (plan->nD > 0 && !grad_weights) fail(DOM_AGG_EINVAL, "grad_weights is NULL");
+        if (plan->nD == 0) return;
+        int dev;
+        require_gfx950(&dev);
+        if (dev != plan->device) fail(DOM_AGG_EINVAL, "plan belongs to device %d, current is %d", plan->device, dev);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const std::vector<uintptr_t> key{2, (uintptr_t)grad_dtype, (uintptr_t)grad_out, (uintptr_t)grad_weights};
+        maybe_graph(plan, key, s, [&](hipStream_t cs) {
+            DevBuf k, v;
+            const void *kp = nullptr;
+            const uint32_t *vp = nullptr;
+            if (plan->E > 0) records_for_call(plan, cs, k, v, &kp, &vp);
+            if (grad_dtype == DOM_AGG_F32) {
+                if (plan->key64) backward_typed<uint64_t, float>(plan, kp, vp, grad_out, grad_weights, cs);
+                else backward_typed<uint32_t, float>(plan, kp, vp, grad_out, grad_weights, cs);
+            } else {
+                if (plan->key64) backward_typed<uint64_t, double>(plan, kp, vp, grad_out, grad_weights, cs);
+                else backward_typed<uint32_t, double>(plan, kp, vp, grad_out, grad_weights, cs);
+            }
+        });
+    });
+}
+
+dom_agg_status dom_agg_plan_get_info(dom_agg_plan_t plan, dom_agg_plan_info *info) {
+    return guarded([&] {
+        if (!plan || !info) fail(DOM_AGG_EINVAL, "NULL argument");
+        std::memset(info, 0, sizeof *info);
+        info->n_inst = plan->n_inst;
+        info->n_data = plan->nD;
+        info->n_query = plan->nQ;
+        info->records = plan->E;
+        info->data_records = plan->E_D;
+        info->m = plan->m;
+        info->key_bits = plan->key_bits;
+        for (int a = 0; a < 3; ++a) info->L[a] = plan->Lmax[a];
+        info->sort_passes = (int32_t)plan->rec_shifts.size();
+        info->digit_bits = kRadixBits;
+        info->sort_tile = kBlock * plan->tune.record_sort_items;
+        info->scan_tile = kBlock * ((plan->tune.scan_items == 8 || plan->key64) ? 8 : 16);
+        info->workspace_bytes = plan->workspace();
+    });
+}
+
+void dom_agg_plan_destroy(dom_agg_plan_t plan) {
+    if (!plan) return;
+    if (plan->gexec) (void)hipGraphExecDestroy(plan->gexec);
+    if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
+    delete plan;
+}
+
+dom_agg_status dom_agg_timing_enable(int enable) {
+    return guarded([&] {
+        std::lock_guard<std::mutex> lk(g_tmu);
+        g_timing = enable != 0;
+        for (auto &t : g_pending) {
+            (void)hipEventSynchronize(t.b);
+            g_event_pool.push_back(t.a);
+            g_event_pool.push_back(t.b);
+        }
+        g_pending.clear();
+        g_totals.clear();
+    });
+}
+
+int dom_agg_timing_read(const char **names, double *total_ms, int64_t *launches, int cap) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    for (auto &t : g_pending) {
+        if (hipEventSynchronize(t.b) != hipSuccess) return -1;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, t.a, t.b) != hipSuccess) return -1;
+        auto it = std::find_if(g_totals.begin(), g_totals.end(),
+                               [&](const KernelTotal &k) { return std::strcmp(k.name, t.name) == 0; });
+        if (it == g_totals.end()) g_totals.push_back({t.name, (double)ms, 1});
+        else {
+            it->ms += ms;
+            it->launches += 1;
+        }
+        g_event_pool.push_back(t.a);
+        g_event_pool.push_back(t.b);
+    }
+    g_pending.clear();
+    const int k = (int)g_totals.size();
+    for (int i = 0; i < k && i < cap; ++i) {
+        if (names) names[i] = g_totals[i].name;
+        if (total_ms) total_ms[i] = g_totals[i].ms;
+        if (launches) launches[i] = g_totals[i].launches;
+    }
+    return k;
+}
+
+}  // extern "C"

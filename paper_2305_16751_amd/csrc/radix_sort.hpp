@@ -1,0 +1,234 @@
+// Stable LSD radix sort of (key, u32 payload) pairs, one kernel launch per
+// 8-bit digit ("onesweep": the digit offsets of every tile come from a
+// decoupled look-back over the tiles before it, so each pass reads and writes
+// the data once).  The per-digit histograms of every pass are computed up
+// front, fused into the kernel that produces the keys.
+//
+// This realises the sorts of the paper's algorithm (Sec. 4: the per-axis
+// sorts of coordinates and the sort of the expanded list; Sec. 5: its order).
+// Stability is what carries the secondary orders: a list emitted in
+// (last coordinate, queries first, ID) order and stably sorted by the
+// bitstring tuple ends up in the Sec. 5 order.
+#pragma once
+
+#include "device_common.hpp"
+
+namespace domagg {
+
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+constexpr int kMaxPasses = 8;  // 64-bit keys
+
+// Status word of one (tile, digit): flag in bits 62..63, count below.
+constexpr uint64_t kDigitCountMask = (1ull << 62) - 1;
+
+// ---------------------------------------------------------------------------
+// Fused histogram: add the digits of `key` for passes [0, passes) to the
+// LDS histogram s_hist[passes][256].  All lanes of the wavefront must call
+// it together; lanes with valid = false contribute nothing.  Lanes sharing
+// the first valid lane's digit are added with one atomic (skewed digits, such
+// as the high digits of the tree-node keys, would otherwise serialise).
+template <class K>
+__device__ __forceinline__ void hist_add(uint32_t *s_hist, K key, bool valid, int passes) {
+    const uint64_t act = __ballot(valid);
+    if (act == 0) return;
+    const int leader = __ffsll((unsigned long long)act) - 1;
+    const int lane = lane_id();
+    for (int p = 0; p < passes; ++p) {
+        const uint32_t d = (uint32_t)(key >> (kRadixBits * p)) & (kRadix - 1);
+        const uint32_t d0 = read_lane_u32(d, leader);
+        const uint64_t same = __ballot(valid && d == d0);
+        if (lane == leader) atomicAdd(&s_hist[p * kRadix + d0], (uint32_t)__popcll(same));
+        if (valid && d != d0) atomicAdd(&s_hist[p * kRadix + d], 1u);
+    }
+}
+
+// Writes the block's LDS histogram to part[blockIdx.x][passes * 256].
+__device__ __forceinline__ void hist_flush(const uint32_t *s_hist, uint32_t *part, int passes) {
+    for (int i = threadIdx.x; i < passes * kRadix; i += blockDim.x)
+        part[(size_t)blockIdx.x * passes * kRadix + i] = s_hist[i];
+}
+
+// Exclusive sum over a block of BLOCK threads; *total gets the block sum.
+template <int BLOCK>
+__device__ __forceinline__ uint32_t block_excl_sum(uint32_t v, uint32_t *s_tmp, uint32_t *total) {
+    const int lane = lane_id(), wave = threadIdx.x / kWave;
+    const uint32_t incl = wave_sum_scan_incl(v);
+    if (lane == kWave - 1) s_tmp[wave] = incl;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < BLOCK / kWave; ++w) {
+        const uint32_t t = s_tmp[w];
+        pre += (w < wave) ? t : 0u;
+        tot += t;
+    }
+    __syncthreads();
+    if (total) *total = tot;
+    return pre + incl - v;
+}
+
+// One block per pass: sums the per-block partial histograms and scans them
+// into exclusive digit bases.  counts/bases are [passes][256].
+__global__ __launch_bounds__(kRadix) void hist_reduce_kernel(const uint32_t *__restrict__ part,
+                                                             int nblocks, int passes,
+                                                             uint32_t *__restrict__ counts,
+                                                             uint32_t *__restrict__ bases) {
+    __shared__ uint32_t s_tmp[kRadix / kWave];
+    const int p = blockIdx.x, d = threadIdx.x;
+    uint32_t sum = 0;
+    for (int b = 0; b < nblocks; ++b) sum += part[((size_t)b * passes + p) * kRadix + d];
+    const uint32_t ex = block_excl_sum<kRadix>(sum, s_tmp, nullptr);
+    counts[p * kRadix + d] = sum;
+    bases[p * kRadix + d] = ex;
+}
+
+// Standalone histogram of an existing key array (used when the producer
+// could not fuse it).
+template <class K, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void hist_kernel(const K *__restrict__ keys, uint64_t n,
+                                                     int passes, uint32_t *__restrict__ part) {
+    __shared__ uint32_t s_hist[kMaxPasses * kRadix];
+    for (int i = threadIdx.x; i < passes * kRadix; i += BLOCK) s_hist[i] = 0;
+    __syncthreads();
+    const uint64_t stride = (uint64_t)gridDim.x * BLOCK;
+    for (uint64_t base = (uint64_t)blockIdx.x * BLOCK; base < n; base += stride) {
+        const uint64_t i = base + threadIdx.x;
+        const bool valid = i < n;
+        const K k = valid ? keys[i] : K(0);
+        hist_add(s_hist, k, valid, passes);
+    }
+    __syncthreads();
+    hist_flush(s_hist, part, passes);
+}
+
+// ---------------------------------------------------------------------------
+// One digit pass.  A workgroup takes the next tile from a ticket counter (so
+// every tile it waits on belongs to a workgroup that is already running),
+// ranks its keys by digit within each wavefront (ballot matching, stable in
+// index order), publishes its per-digit counts, looks back over earlier tiles
+// for the per-digit offsets (one thread per digit), stages keys and then
+// payloads in LDS in local digit order and writes them out in runs.
+//
+// n < 2^32 - 2*TILE.  status: [tiles][256] words, zero before the launch;
+// ticket: zero before the launch.  digit_base: [256] exclusive bases of the
+// pass's digits over the whole array.
+template <class K, int BLOCK, int ITEMS>
+__global__ __launch_bounds__(BLOCK) void onesweep_kernel(
+    const K *__restrict__ kin, const uint32_t *__restrict__ vin, K *__restrict__ kout,
+    uint32_t *__restrict__ vout, uint32_t n, int shift, const uint32_t *__restrict__ digit_base,
+    uint64_t *__restrict__ status, uint32_t *__restrict__ ticket) {
+    constexpr int TILE = BLOCK * ITEMS;
+    constexpr int WAVES = BLOCK / kWave;
+    static_assert(BLOCK >= kRadix, "one thread per digit");
+    static_assert(ITEMS <= 32, "");
+
+    __shared__ union {
+        K keys[TILE];
+        uint32_t vals[TILE];
+    } s_stage;
+    __shared__ uint32_t s_whist[WAVES][kRadix];  // counts, then exclusive over waves
+    __shared__ uint32_t s_dstart[kRadix];        // tile-local start of each digit
+    __shared__ uint32_t s_goff[kRadix];          // global start minus local start
+    __shared__ uint32_t s_tmp[WAVES];
+    __shared__ uint32_t s_tile;
+
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    for (int i = tid; i < WAVES * kRadix; i += BLOCK) (&s_whist[0][0])[i] = 0;
+    if (tid == 0) s_tile = atomicAdd(ticket, 1u);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const uint64_t wbase = (uint64_t)tile * TILE + (uint64_t)wave * kWave * ITEMS;
+
+    // Wave-striped loads: item i of lane l is element wbase + 64 i + l, so
+    // ranking items in order i keeps index order within the wavefront.
+    K key[ITEMS];
+    uint32_t val[ITEMS];
+    uint32_t loc[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint64_t idx = wbase + (uint64_t)i * kWave + lane;
+        if (idx < n) {
+            key[i] = kin[idx];
+            val[i] = vin[idx];
+        } else {
+            key[i] = ~K(0);  // digit 255 at every shift: sorts after all real keys of the tile
+            val[i] = 0;
+        }
+    }
+
+    const uint64_t below_mask = lanemask_lt();
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t d = (uint32_t)(key[i] >> shift) & (kRadix - 1);
+        const uint64_t peers = match_digit<kRadixBits>(d);
+        const uint32_t below = (uint32_t)__popcll(peers & below_mask);
+        const uint32_t cnt = s_whist[wave][d];
+        loc[i] = cnt + below;
+        if (below == 0) s_whist[wave][d] = cnt + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+
+    uint32_t count = 0;
+    if (tid < kRadix) {
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) {
+            const uint32_t c = s_whist[w][tid];
+            s_whist[w][tid] = count;
+            count += c;
+        }
+        const uint64_t flag = tile == 0 ? kFlagInclusive : kFlagAggregate;
+        store_agent(&status[(uint64_t)tile * kRadix + tid], (flag << 62) | count);
+    }
+    const uint32_t dstart = block_excl_sum<BLOCK>(tid < kRadix ? count : 0u, s_tmp, nullptr);
+    if (tid < kRadix) {
+        s_dstart[tid] = dstart;
+        uint32_t excl = 0;
+        if (tile > 0) {
+            uint32_t t = tile - 1;
+            for (;;) {
+                uint64_t w;
+                while (((w = load_agent(&status[(uint64_t)t * kRadix + tid])) >> 62) == 0)
+                    __builtin_amdgcn_s_sleep(1);
+                excl += (uint32_t)(w & kDigitCountMask);
+                if ((w >> 62) == kFlagInclusive) break;
+                --t;
+            }
+            store_agent(&status[(uint64_t)tile * kRadix + tid],
+                        ((uint64_t)kFlagInclusive << 62) | (uint64_t)(excl + count));
+        }
+        s_goff[tid] = digit_base[tid] + excl - dstart;
+    }
+    __syncthreads();
+
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t d = (uint32_t)(key[i] >> shift) & (kRadix - 1);
+        const uint32_t lp = s_dstart[d] + s_whist[wave][d] + loc[i];
+        s_stage.keys[lp] = key[i];
+        loc[i] = lp;
+    }
+    __syncthreads();
+
+    uint32_t gpos[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t p = (uint32_t)(i * BLOCK + tid);
+        const K k = s_stage.keys[p];
+        const uint32_t d = (uint32_t)(k >> shift) & (kRadix - 1);
+        const uint32_t g = s_goff[d] + p;
+        gpos[i] = g;
+        if (g < n) kout[g] = k;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) s_stage.vals[loc[i]] = val[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t p = (uint32_t)(i * BLOCK + tid);
+        if (gpos[i] < n) vout[gpos[i]] = s_stage.vals[p];
+    }
+}
+
+}  // namespace domagg

@@ -1,0 +1,91 @@
+// Tile choices of the kernels and their cache.  The tuner itself (timing the
+// candidates on a plan's own records) lives with the plan code; this header
+// holds the choice, its defaults and the persistent cache keyed by
+// (gfx950, m, record key bits, ceil(log2 E)).
+//
+// Cache file: $DOM_AGG_TUNE_CACHE, else $HOME/.cache/dom_agg_tune.txt; one
+// line per key: "m key_bits log2E record_sort_items scan_items".
+// DOM_AGG_TUNE=0 disables tuning (defaults are used).
+#pragma once
+
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+
+namespace domagg {
+
+struct TuneChoice {
+    int record_sort_items = 16;  // onesweep tile = 256 * items
+    int point_sort_items = 16;
+    int scan_items = 16;         // segmented-scan tile = 256 * items (8 forced for 64-bit keys)
+};
+
+inline TuneChoice default_tune() { return TuneChoice{}; }
+
+using TuneKey = std::tuple<int, int, int>;
+
+class TuneCache {
+  public:
+    static TuneCache &get() {
+        static TuneCache c;
+        return c;
+    }
+    bool enabled() const {
+        const char *e = std::getenv("DOM_AGG_TUNE");
+        return !(e && e[0] == '0');
+    }
+    bool lookup(const TuneKey &k, TuneChoice *out) {
+        std::lock_guard<std::mutex> lk(mu_);
+        load_once();
+        auto it = map_.find(k);
+        if (it == map_.end()) return false;
+        *out = it->second;
+        return true;
+    }
+    void store(const TuneKey &k, const TuneChoice &c) {
+        std::lock_guard<std::mutex> lk(mu_);
+        load_once();
+        map_[k] = c;
+        const std::string p = path();
+        if (p.empty()) return;
+        if (FILE *f = std::fopen(p.c_str(), "w")) {
+            for (auto &kv : map_)
+                std::fprintf(f, "%d %d %d %d %d\n", std::get<0>(kv.first), std::get<1>(kv.first),
+                             std::get<2>(kv.first), kv.second.record_sort_items, kv.second.scan_items);
+            std::fclose(f);
+        }
+    }
+
+  private:
+    std::string path() const {
+        if (const char *e = std::getenv("DOM_AGG_TUNE_CACHE")) return e;
+        const char *h = std::getenv("HOME");
+        if (!h) return "";
+        return std::string(h) + "/.cache/dom_agg_tune.txt";
+    }
+    void load_once() {
+        if (loaded_) return;
+        loaded_ = true;
+        const std::string p = path();
+        if (p.empty()) return;
+        FILE *f = std::fopen(p.c_str(), "r");
+        if (!f) return;
+        int m, kb, le, rs, sc;
+        while (std::fscanf(f, "%d %d %d %d %d", &m, &kb, &le, &rs, &sc) == 5) {
+            if ((rs != 8 && rs != 16) || (sc != 8 && sc != 16)) continue;
+            TuneChoice c;
+            c.record_sort_items = rs;
+            c.scan_items = sc;
+            map_[TuneKey{m, kb, le}] = c;
+        }
+        std::fclose(f);
+    }
+    std::mutex mu_;
+    bool loaded_ = false;
+    std::map<TuneKey, TuneChoice> map_;
+};
+
+}  // namespace domagg

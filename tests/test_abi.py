@@ -1,0 +1,119 @@
+"""The C-ABI library loads, exports every symbol include/dom_agg.h declares,
+and rejects invalid arguments before touching the GPU.  No GPU needed: every
+call here either fails validation or (with valid arguments and no device)
+reports ENODEV."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dom_agg.h")
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2305_16751_amd import binding
+    from paper_2305_16751_amd.build import lib_path, build
+    if not os.path.exists(lib_path()):
+        build()
+    binding.load()
+    return binding
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:[A-Za-z_][\w\s\*]*?)\b(dom_agg_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_header_declares_exports(B):
+    decl = declared_functions()
+    assert set(decl) == set(B.EXPORTS), decl
+
+
+def test_library_exports_every_declared_symbol(B):
+    lib = B.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_exported_symbols_via_nm(B):
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--defined-only", B.lib_path()], capture_output=True, text=True).stdout
+    syms = {ln.split()[-1] for ln in out.splitlines() if ln.strip()}
+    for name in declared_functions():
+        assert name in syms, name
+
+
+def test_status_strings(B):
+    lib = B.load()
+    for st in range(8):
+        assert lib.dom_agg_status_string(st)
+    assert lib.dom_agg_status_string(99) == b"unknown status"
+
+
+def _plan(B, m=2, dt=None, d=1, q=1, n_inst=1, doff=None, qoff=None, flags=0, null_plan=False):
+    lib = B.load()
+    dt = B.F32 if dt is None else dt
+    doff = np.array([0, 4] if doff is None else doff, dtype=np.int64)
+    qoff = np.array([0, 3] if qoff is None else qoff, dtype=np.int64)
+    h = ctypes.c_void_p()
+    st = lib.dom_agg_plan(None if null_plan else ctypes.byref(h), m, dt,
+                          ctypes.c_void_p(d) if d else None, ctypes.c_void_p(q) if q else None,
+                          n_inst, doff.ctypes.data_as(ctypes.c_void_p), qoff.ctypes.data_as(ctypes.c_void_p),
+                          flags, None)
+    return st, h
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(m=0), "EINVAL"), (dict(m=5), "EINVAL"), (dict(null_plan=True), "EINVAL"),
+    (dict(dt=3), "EUNSUPPORTED"), (dict(dt=1), "EUNSUPPORTED"), (dict(dt=9), "EINVAL"),
+    (dict(n_inst=0), "EINVAL"), (dict(doff=[1, 4]), "EINVAL"), (dict(qoff=[0, -1]), "EINVAL"),
+    (dict(d=0), "EINVAL"), (dict(q=0), "EINVAL"), (dict(flags=1), "EINVAL"), (dict(flags=64), "EINVAL"),
+    (dict(doff=[0, 1 << 30], qoff=[0, 1 << 30]), "ETOOBIG"),
+    (dict(n_inst=2, doff=[0, 3, 2], qoff=[0, 1, 3]), "EINVAL"),
+])
+def test_plan_argument_validation(B, kw, status):
+    st, _ = _plan(B, **kw)
+    assert B.STATUS_NAMES[st] == status
+    assert B.load().dom_agg_last_error()
+
+
+def test_forward_backward_validation(B):
+    lib = B.load()
+    assert lib.dom_agg_forward(None, 0, B.F32, None, None, None) == B.EINVAL
+    assert lib.dom_agg_backward(None, B.F32, None, None, None) == B.EINVAL
+    info = B.PlanInfo()
+    assert lib.dom_agg_plan_get_info(None, ctypes.byref(info)) == B.EINVAL
+    lib.dom_agg_plan_destroy(None)
+
+
+def test_allocator_hook_pairs(B):
+    lib = B.load()
+    alloc = B.ALLOC_FN(lambda n, s, c: None)
+    assert lib.dom_agg_set_allocator(alloc, ctypes.cast(None, B.RELEASE_FN), None) == B.EINVAL
+    assert lib.dom_agg_set_allocator(ctypes.cast(None, B.ALLOC_FN), ctypes.cast(None, B.RELEASE_FN), None) == B.OK
+
+
+def test_valid_plan_without_device_reports_enodev(B):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    st, _ = _plan(B)
+    assert B.STATUS_NAMES[st] == "ENODEV"
+
+
+def test_timing_api(B):
+    lib = B.load()
+    assert lib.dom_agg_timing_enable(1) == B.OK
+    assert B.timing_read() == {}
+    assert lib.dom_agg_timing_enable(0) == B.OK
+
+
+def test_python_front_end_fails_loudly_without_library(tmp_path):
+    from paper_2305_16751_amd import binding
+    with pytest.raises(RuntimeError, match="has not been built"):
+        binding.load(str(tmp_path / "missing.so"))

@@ -1,0 +1,217 @@
+"""HIP path vs the CPU oracle, element by element, on seeded inputs.
+
+Every call goes through the C-ABI (via the ctypes front end).  Integer F and
+max are compared bit-exactly; fp32 sums per query within
+2e-6 * (sum of |w| over the dominated data points), against fp64.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from gpu_helpers import DEV, check_exact, check_fp, expected, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    from paper_2305_16751_amd import binding
+    binding.load()
+    assert torch.cuda.is_available()
+
+
+def _plan(c, **kw):
+    from paper_2305_16751_amd import DomAggPlan
+    return DomAggPlan(to_dev(c.D), to_dev(c.Q), **kw)
+
+
+def _run_and_check(c, op, wdtype, **plan_kw):
+    plan = _plan(c, **plan_kw)
+    w = None if op == "count" else c.w.astype(wdtype)
+    out = plan.forward(None if w is None else to_dev(w), op)
+    want, E, L = oracle.construction(c.m, c.D, c.Q, None if w is None else
+                                     w.astype(np.float64 if np.dtype(wdtype).kind == "f" else np.int64),
+                                     op, weight_dtype=wdtype if w is not None else None, return_stats=True)
+    info = plan.info()
+    assert info["records"] == E, (info["records"], E)
+    assert info["L"] == L, (info["L"], L)
+    if op == "sum" and np.dtype(wdtype).kind == "f":
+        scale = oracle.construction(c.m, c.D, c.Q, np.abs(w.astype(np.float64)), "sum")
+        check_fp(out, want, scale, f"{c.name} {op} {wdtype}")
+    else:
+        check_exact(out, want, f"{c.name} {op} {wdtype}")
+    return plan, out
+
+
+# ---------------------------------------------------------------------------
+# worked example
+
+
+def test_worked_example(golden_dir):
+    import os
+    rows = {}
+    for line in open(os.path.join(golden_dir, "worked_example_2d.txt")):
+        if line.strip() and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            rows[k.strip()] = v.split()
+    D = np.array([s.split(",") for s in rows["D"]], dtype=np.int32)
+    Q = np.array([s.split(",") for s in rows["Q"]], dtype=np.int32)
+    w = np.array(rows["w"], dtype=np.int64)
+    c = workloads.Case("worked", 2, D, Q, w)
+    plan = _plan(c)
+    assert plan.info()["records"] == int(rows["E"][0])
+    check_exact(plan.forward(to_dev(w), "sum"), np.array(rows["sum"], dtype=np.int64), "sum")
+    check_exact(plan.forward(None, "count"), np.array(rows["count"], dtype=np.int64), "count")
+    mx = plan.forward(to_dev(w.astype(np.float32)), "max").cpu().numpy()
+    np.testing.assert_array_equal(mx, np.array(rows["max"], dtype=np.float32))
+
+
+# ---------------------------------------------------------------------------
+# small random inputs with heavy ties, every m / op / dtype
+
+
+CASES = []
+for m in (1, 2, 3, 4):
+    for coord, alpha in (("int", 6), ("int", 1000), ("f32", 16), ("f32", None)):
+        CASES.append((m, coord, alpha))
+
+
+@pytest.mark.parametrize("m,coord,alpha", CASES)
+def test_small_int_weights(m, coord, alpha):
+    n = {1: 3000, 2: 2500, 3: 900, 4: 300}[m]
+    c = workloads.small_case(100 + m * 7 + (alpha or 0), m, n, n - 37, alphabet=alpha, coord=coord, weight="int64")
+    plan, _ = _run_and_check(c, "sum", np.int64)
+    want = expected(m, c.D, c.Q, None, "count")
+    check_exact(plan.forward(None, "count"), want, "count")
+    check_exact(plan.forward(to_dev(c.w), "max"), expected(m, c.D, c.Q, c.w, "max"), "max i64")
+    w32 = c.w.astype(np.int32)
+    check_exact(plan.forward(to_dev(w32), "sum"), expected(m, c.D, c.Q, w32, "sum", np.int32), "sum i32")
+    check_exact(plan.forward(to_dev(w32), "max"), expected(m, c.D, c.Q, w32, "max", np.int32), "max i32")
+
+
+@pytest.mark.parametrize("m,coord,alpha", CASES)
+def test_small_float_weights(m, coord, alpha):
+    n = {1: 3000, 2: 2500, 3: 900, 4: 300}[m]
+    c = workloads.small_case(200 + m * 7 + (alpha or 0), m, n - 11, n, alphabet=alpha, coord=coord, weight="f32")
+    plan = _plan(c)
+    w64 = c.w.astype(np.float64)
+    scale = oracle.construction(m, c.D, c.Q, np.abs(w64), "sum")
+    check_fp(plan.forward(to_dev(c.w), "sum"), oracle.construction(m, c.D, c.Q, w64, "sum"), scale, "sum f32")
+    check_fp(plan.forward(to_dev(w64), "sum"), oracle.construction(m, c.D, c.Q, w64, "sum"), scale, "sum f64",
+             tol=1e-12)
+    check_exact(plan.forward(to_dev(c.w), "max"), oracle.construction(m, c.D, c.Q, w64, "max"), "max f32")
+    check_exact(plan.forward(to_dev(w64), "max"), oracle.construction(m, c.D, c.Q, w64, "max"), "max f64")
+    g = np.random.default_rng(m).standard_normal(c.Q.shape[0]).astype(np.float32)
+    gw = plan.backward(to_dev(g))
+    want = oracle.transposed_sum(m, c.D, c.Q, g.astype(np.float64))
+    gs = oracle.transposed_sum(m, c.D, c.Q, np.abs(g.astype(np.float64)))
+    check_fp(gw, want, gs, "grad f32")
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 63, 64, 65, 2047, 2048, 2049, 4095, 4096, 4097, 10007])
+def test_ragged_sizes(n):
+    c = workloads.small_case(n, 2, n, max(n // 2, 1), alphabet=max(n, 4), coord="int", weight="int64")
+    _run_and_check(c, "sum", np.int64)
+
+
+def test_many_tiles_2d_int():
+    """Records span hundreds of sort and scan tiles with a ragged tail."""
+    c = workloads.small_case(77, 2, 40001, 39999, alphabet=1 << 20, coord="int", weight="int64")
+    _run_and_check(c, "sum", np.int64)
+
+
+# ---------------------------------------------------------------------------
+# edge cases
+
+
+def test_empty_data_and_queries():
+    from paper_2305_16751_amd import DomAggPlan
+    q = to_dev(np.random.default_rng(0).random((50, 2), dtype=np.float32))
+    d0 = torch.empty((0, 2), dtype=torch.float32, device=DEV)
+    plan = DomAggPlan(d0, q)
+    assert plan.forward(torch.empty(0, device=DEV), "sum").abs().max().item() == 0
+    assert (plan.forward(None, "count") == 0).all()
+    mx = plan.forward(torch.empty(0, dtype=torch.int32, device=DEV), "max")
+    assert (mx == np.iinfo(np.int32).min).all()
+    plan2 = DomAggPlan(q, d0)
+    assert plan2.forward(torch.ones(50, device=DEV), "sum").numel() == 0
+    assert plan2.backward(torch.empty(0, device=DEV)).abs().max().item() == 0
+
+
+def test_all_points_equal_gives_identity():
+    from paper_2305_16751_amd import DomAggPlan
+    p = torch.ones((100, 3), dtype=torch.int32, device=DEV)
+    plan = DomAggPlan(p, p)
+    assert plan.info()["records"] == 0
+    assert (plan.forward(torch.ones(100, dtype=torch.int64, device=DEV), "sum") == 0).all()
+    mx = plan.forward(torch.ones(100, dtype=torch.float32, device=DEV), "max")
+    assert torch.isneginf(mx).all()
+
+
+def test_nan_coordinate_rejected():
+    from paper_2305_16751_amd import DomAggPlan, DomAggError
+    d = torch.rand((10, 2), device=DEV)
+    d[3, 1] = float("nan")
+    with pytest.raises(DomAggError, match="ENAN"):
+        DomAggPlan(d, torch.rand((5, 2), device=DEV))
+
+
+def test_signed_zero_and_infinities():
+    D = np.array([[-0.0, 1.0], [0.0, -np.inf], [np.inf, 0.0], [-1.0, -1.0]], dtype=np.float32)
+    Q = np.array([[0.0, 2.0], [np.inf, np.inf], [1e-30, 0.5], [-0.0, 3.0]], dtype=np.float32)
+    w = np.array([1, 2, 4, 8], dtype=np.int64)
+    c = workloads.Case("zeros", 2, D, Q, w)
+    _run_and_check(c, "sum", np.int64)
+
+
+def test_int32_extremes():
+    rng = np.random.default_rng(5)
+    vals = np.array([np.iinfo(np.int32).min, -1, 0, 1, np.iinfo(np.int32).max], dtype=np.int32)
+    D = rng.choice(vals, size=(500, 2)).astype(np.int32)
+    Q = rng.choice(vals, size=(400, 2)).astype(np.int32)
+    c = workloads.Case("extremes", 2, D, Q, rng.integers(0, 100, 500).astype(np.int64))
+    _run_and_check(c, "sum", np.int64)
+
+
+# ---------------------------------------------------------------------------
+# modes
+
+
+def test_recompute_matches_keep():
+    c = workloads.small_case(9, 3, 2000, 1800, alphabet=200, coord="int", weight="int64")
+    a = _plan(c).forward(to_dev(c.w), "sum")
+    p = _plan(c, recompute=True)
+    b = p.forward(to_dev(c.w), "sum")
+    check_exact(b, a.cpu().numpy(), "recompute fwd")
+    g = np.random.default_rng(1).standard_normal(c.Q.shape[0])
+    ga = _plan(c).backward(to_dev(g))
+    gb = p.backward(to_dev(g))
+    np.testing.assert_allclose(gb.cpu().numpy(), ga.cpu().numpy(), rtol=1e-12, atol=1e-9)
+
+
+def test_graph_replay_matches_eager():
+    c = workloads.small_case(10, 2, 30000, 30000, alphabet=1 << 16, coord="int", weight="int64")
+    eager = _plan(c).forward(to_dev(c.w), "sum").cpu().numpy()
+    p = _plan(c, graph=True)
+    w = to_dev(c.w)
+    out = torch.empty(c.Q.shape[0], dtype=torch.int64, device=DEV)
+    for r in range(4):
+        p.forward(w, "sum", out=out)
+        torch.cuda.synchronize()
+        check_exact(out, eager, f"replay {r}")
+        out.fill_(-7)  # eager work between replays
+        torch.cuda.synchronize()
+
+
+def test_autograd_function():
+    from paper_2305_16751_amd import dom_agg
+    c = workloads.small_case(11, 2, 3000, 2500, alphabet=None, coord="f32", weight="f32")
+    w = to_dev(c.w).requires_grad_(True)
+    out = dom_agg(to_dev(c.D), to_dev(c.Q), w, "sum")
+    coef = np.random.default_rng(3).standard_normal(c.Q.shape[0]).astype(np.float32)
+    (out * to_dev(coef)).sum().backward()
+    want = oracle.transposed_sum(2, c.D, c.Q, coef.astype(np.float64))
+    scale = oracle.transposed_sum(2, c.D, c.Q, np.abs(coef.astype(np.float64)))
+    check_fp(w.grad, want, scale, "autograd grad")
