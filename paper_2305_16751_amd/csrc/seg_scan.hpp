@@ -81,7 +81,9 @@ __global__ __launch_bounds__(BLOCK) void seg_scan_kernel(P p, uint64_t n,
             acc = p.combine(acc, v[j]);
             prev = cur;
         } else {
+            // past the end: marks the previous element as the last of its segment
             v[j] = p.identity();
+            heads |= 1u << j;
         }
     }
     {
@@ -98,8 +100,12 @@ __global__ __launch_bounds__(BLOCK) void seg_scan_kernel(P p, uint64_t n,
     uint32_t f = tflag;
     V a = acc;
     wave_seg_scan_incl(p, f, a);
-    const V ex_v = lane ? read_lane(a, lane - 1) : p.identity();
-    const uint32_t ex_f = lane ? read_lane_u32(f, lane - 1) : 0u;
+    // every lane takes part in the permutes; lane 0 then drops what it read
+    const int src = lane ? lane - 1 : 0;
+    const V up_v = read_lane(a, src);
+    const uint32_t up_f = read_lane_u32(f, src);
+    const V ex_v = lane ? up_v : p.identity();
+    const uint32_t ex_f = lane ? up_f : 0u;
     if (lane == kWave - 1) {
         s_wval[wave] = a;
         s_wflag[wave] = f;
