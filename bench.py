@@ -1,0 +1,270 @@
+#!/usr/bin/env python3
+"""Benchmark of dominance aggregation on one MI355X.
+
+One step = the whole path on one batch of synthetic input: the coordinate
+phase (ranks, flat map, record sort) plus the forward segmented scan and
+regrouping, i.e. dom_agg_plan + dom_agg_forward, with inputs resident in HBM.
+Default workload: m = 2, |D| = |Q| = 2^24 float32 coordinates U[0,1), float32
+weights N(0,1), F = sum (fp32 accumulation).
+
+Prints one JSON line.  Per-kernel times come from HIP events the library
+records around each launch on the stream it runs on; the roofline entry is
+the record sort's onesweep pass (the dominant kernel).  The CPU baseline is
+the oracle (plain sequential C of the paper's construction) timed on a
+bounded sample of the same distribution.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "(|D|+|Q|)/s m=2,3 dominance sum; fwd+bwd & batched vs plain; HBM GB/s frac"
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def key_bytes(info):
+    return 4 if info["key_bits"] <= 32 else 8
+
+
+def stage_table(kern, steps, info, n, nax, wbytes=4):
+    """Per-kernel average time and, where the kernel has a fixed algorithmic
+    byte count, its achieved rate."""
+    E = info["records"]
+    ED = info["data_records"]
+    EQ = E - ED
+    kb = key_bytes(info)
+    model = {
+        "flatmap_emit": E * (kb + 4) + n * (8 + 4 + 4 * nax),
+        "forward_scan": E * (kb + 4) + ED * wbytes + EQ * wbytes,
+        "backward_scan": E * (kb + 4) + EQ * wbytes + ED * wbytes,
+    }
+    out = {}
+    for name, (ms, cnt) in sorted(kern.items(), key=lambda kv: -kv[1][0]):
+        avg = ms / max(cnt, 1)
+        row = {"ms_per_step": round(ms / steps, 4), "launches_per_step": round(cnt / steps, 2),
+               "avg_ms_per_launch": round(avg, 5)}
+        b = None
+        if name.startswith("onesweep_records"):
+            b = 2 * E * (kb + 4)
+        elif name in model:
+            b = model[name]
+        if b is not None and avg > 0:
+            row["algorithmic_GB_per_launch"] = round(b / 1e9, 4)
+            row["GBps"] = round(b / (avg * 1e-3) / 1e9, 1)
+            row["frac_of_8TBps"] = round(b / (avg * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
+        out[name] = row
+    return out
+
+
+def time_steps(fn, steps, warmup):
+    import torch
+    from paper_2305_16751_amd import binding
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    binding.timing_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern = binding.timing_read()
+    binding.timing_enable(False)
+    return (t1 - t0), kern
+
+
+def run_plain(case, steps, warmup, op="sum"):
+    import torch
+    from paper_2305_16751_amd import DomAggPlan
+    d = torch.from_numpy(case.D).cuda()
+    q = torch.from_numpy(case.Q).cuda()
+    w = torch.from_numpy(case.w).cuda()
+    out = torch.empty(q.shape[0], dtype=torch.float32 if case.w.dtype == np.float32 else torch.int64,
+                      device="cuda")
+    info = {}
+
+    def step():
+        plan = DomAggPlan(d, q)
+        plan.forward(w, op, out=out)
+        if not info:
+            info.update(plan.info())
+        plan.close()
+
+    T, kern = time_steps(step, steps, warmup)
+    return T, kern, info, out
+
+
+def roofline_entry(kern, info):
+    rec = {k: v for k, v in kern.items() if k.startswith("onesweep_records")}
+    if not rec:
+        return None
+    name, (ms, cnt) = max(rec.items(), key=lambda kv: kv[1][0])
+    avg_s = ms / cnt * 1e-3
+    E = info["records"]
+    b = 2 * E * (key_bytes(info) + 4)
+    ach = b / avg_s / 1e9
+    return {"bound": "hbm", "kernel": name, "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None,
+            "bytes_per_launch": b, "avg_launch_ms": round(avg_s * 1e3, 5),
+            "bytes_model": "2 * E * (key bytes + 4 payload bytes): read and write of every record per pass"}
+
+
+def cpu_baseline(n_sample=1 << 19):
+    import oracle
+    import workloads
+    c = workloads.f32_uniform(2, n_sample, workloads.BASE_SEED + 99, "sample")
+    w64 = c.w.astype(np.float64)
+    t0 = time.perf_counter()
+    oracle.construction(2, c.D, c.Q, w64, "sum")
+    dt = time.perf_counter() - t0
+    return {"value": round(2 * n_sample / dt, 1), "unit": "(|D|+|Q|)/s", "cores": 1, "kind": "oracle",
+            "sample": f"m=2, |D|=|Q|={n_sample}, float32 U[0,1) coordinates, float32 N(0,1) weights, "
+                      f"fp64 sequential construction (Sec. 4 + Sec. 5), {dt:.2f} s"}
+
+
+def extra_m3(steps):
+    import workloads
+    c = workloads.f32_3d_1m()
+    T, kern, info, _ = run_plain(c, steps, 2)
+    return {"workload": "f32_3d_1m", "value": round(c.n * steps / T, 1), "ms_per_step": round(T / steps * 1e3, 3),
+            "records": info["records"], "key_bits": info["key_bits"],
+            "stages": stage_table(kern, steps, info, c.n, 2)}
+
+
+def extra_fwd_bwd(steps):
+    import torch
+    import workloads
+    from paper_2305_16751_amd import DomAggPlan
+    c = workloads.f32_2d_4m_grad()
+    d = torch.from_numpy(c.D).cuda()
+    q = torch.from_numpy(c.Q).cuda()
+    w = torch.from_numpy(c.w).cuda()
+    g = torch.from_numpy(c.c).cuda()
+    out = torch.empty(q.shape[0], device="cuda")
+    gw = torch.empty(d.shape[0], device="cuda")
+
+    def fwd():
+        p = DomAggPlan(d, q)
+        p.forward(w, "sum", out=out)
+        p.close()
+
+    def fwd_bwd():
+        p = DomAggPlan(d, q)
+        p.forward(w, "sum", out=out)
+        p.backward(g, out=gw)
+        p.close()
+
+    Tf, _ = time_steps(fwd, steps, 2)
+    Tb, kern = time_steps(fwd_bwd, steps, 2)
+    return {"workload": "f32_2d_4m_grad", "fwd_ms": round(Tf / steps * 1e3, 3),
+            "fwd_bwd_ms": round(Tb / steps * 1e3, 3), "ratio": round(Tb / Tf, 3),
+            "backward_scan_ms": round(kern.get("backward_scan", (0, 1))[0] / steps, 4)}
+
+
+def extra_batched(reps):
+    import torch
+    import workloads
+    from paper_2305_16751_amd import DomAggPlan
+    c = workloads.batched_int2d()
+    d = torch.from_numpy(c.D).cuda()
+    q = torch.from_numpy(c.Q).cuda()
+    w = torch.from_numpy(c.w).cuda()
+    out = torch.empty(q.shape[0], dtype=torch.int64, device="cuda")
+
+    def batched():
+        p = DomAggPlan(d, q, c.d_offsets, c.q_offsets, graph=True)
+        p.forward(w, "sum", out=out)
+        p.close()
+
+    Tb, _ = time_steps(batched, reps, 1)
+    doff, qoff = c.d_offsets, c.q_offsets
+
+    def per_instance():
+        for k in range(len(doff) - 1):
+            p = DomAggPlan(d[doff[k]:doff[k + 1]], q[qoff[k]:qoff[k + 1]])
+            p.forward(w[doff[k]:doff[k + 1]], "sum", out=out[qoff[k]:qoff[k + 1]])
+            p.close()
+
+    Tp, _ = time_steps(per_instance, 1, 1)
+    tb, tp = Tb / reps, Tp
+    return {"workload": "batched_int2d", "instances": len(doff) - 1, "points": c.n,
+            "batched_ms": round(tb * 1e3, 3), "per_instance_ms": round(tp * 1e3, 3),
+            "batched_value": round(c.n / tb, 1), "per_instance_value": round(c.n / tp, 1),
+            "speedup": round(tp / tb, 2)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-extras", action="store_true", help="only the headline workload")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 19)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads
+    assert torch.cuda.is_available(), "no GPU"
+    log(f"device: {torch.cuda.get_device_name(0)}")
+
+    case = workloads.f32_2d_16m()
+    log(f"headline: {case.name} m={case.m} |D|={case.D.shape[0]} |Q|={case.Q.shape[0]}")
+    T, kern, info, _ = run_plain(case, args.steps, args.warmup)
+    value = case.n * args.steps / T
+    log(f"headline: {T / args.steps * 1e3:.3f} ms/step, {value:.4g} (|D|+|Q|)/s, E={info['records']}")
+    result = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "(|D|+|Q|)/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(T / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": case.name, "m": case.m, "n_data": int(case.D.shape[0]),
+                   "n_query": int(case.Q.shape[0]), "op": "sum", "coords": "float32 U[0,1)",
+                   "weights": "float32 N(0,1)", "records": info["records"], "key_bits": info["key_bits"],
+                   "sort_passes": info["sort_passes"], "sort_tile": info["sort_tile"],
+                   "scan_tile": info["scan_tile"], "step": "dom_agg_plan + dom_agg_forward"},
+        "roofline": roofline_entry(kern, info),
+    }
+    extra = {"stages": stage_table(kern, args.steps, info, case.n, case.m - 1)}
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on a sample) ...")
+        result["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+    if not args.no_extras:
+        for name, fn in (("m3", lambda: extra_m3(5)), ("fwd_bwd", lambda: extra_fwd_bwd(5)),
+                         ("batched", lambda: extra_batched(3))):
+            log(f"extra: {name} ...")
+            try:
+                extra[name] = fn()
+            except Exception as e:  # an extra must not hide the headline line
+                extra[name] = {"error": repr(e)}
+            log(f"extra: {name}: {json.dumps(extra[name])[:300]}")
+    result["extra"] = extra
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

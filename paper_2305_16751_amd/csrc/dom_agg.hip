@@ -304,28 +304,33 @@ void clear_lookback(uint64_t *status, uint64_t words, uint32_t *ticket, hipStrea
 // ---------------------------------------------------------------------------
 // Radix sort driver.
 
-template <class K>
+template <class K, int ROLE>
 const char *onesweep_name(int items) {
-    if constexpr (sizeof(K) == 4) return items == 8 ? "onesweep_u32_t2048" : "onesweep_u32_t4096";
-    else return items == 8 ? "onesweep_u64_t2048" : "onesweep_u64_t4096";
+    if constexpr (ROLE == 1) {
+        if constexpr (sizeof(K) == 4) return items == 8 ? "onesweep_records_u32_t2048" : "onesweep_records_u32_t4096";
+        else return items == 8 ? "onesweep_records_u64_t2048" : "onesweep_records_u64_t4096";
+    } else {
+        if constexpr (sizeof(K) == 4) return items == 8 ? "onesweep_points_u32_t2048" : "onesweep_points_u32_t4096";
+        else return items == 8 ? "onesweep_points_u64_t2048" : "onesweep_points_u64_t4096";
+    }
 }
 
-template <class K, int ITEMS>
+template <class K, int ITEMS, int ROLE>
 void onesweep_launch(const K *kin, const uint32_t *vin, K *kout, uint32_t *vout, uint32_t n,
                      int shift, const uint32_t *bases, uint64_t *status, uint32_t *ticket,
                      hipStream_t s) {
     constexpr int TILE = kBlock * ITEMS;
     const unsigned tiles = (unsigned)ceil_div(n, TILE);
     clear_lookback(status, (uint64_t)tiles * kRadix, ticket, s);
-    launch(onesweep_name<K>(ITEMS), s, [&] {
-        onesweep_kernel<K, kBlock, ITEMS><<<tiles, kBlock, 0, s>>>(kin, vin, kout, vout, n, shift,
-                                                                   bases, status, ticket);
+    launch(onesweep_name<K, ROLE>(ITEMS), s, [&] {
+        onesweep_kernel<K, kBlock, ITEMS, ROLE><<<tiles, kBlock, 0, s>>>(kin, vin, kout, vout, n, shift,
+                                                                         bases, status, ticket);
     });
 }
 
 // Sorts (kA, vA) by the listed digit shifts; returns true when the result
 // ended up in (kB, vB).  bases: [passes][256] (pass p at shift 8p).
-template <class K>
+template <class K, int ROLE>
 bool radix_sort(K *kA, uint32_t *vA, K *kB, uint32_t *vB, uint64_t n, const std::vector<int> &shifts,
                 const uint32_t *bases, int items, hipStream_t s) {
     if (n == 0 || shifts.empty()) return false;
@@ -341,11 +346,11 @@ bool radix_sort(K *kA, uint32_t *vA, K *kB, uint32_t *vB, uint64_t n, const std:
         uint32_t *vo = inB ? vA : vB;
         const uint32_t *b = bases + (sh / kRadixBits) * kRadix;
         if (items == 8)
-            onesweep_launch<K, 8>(ki, vi, ko, vo, (uint32_t)n, sh, b, status.as<uint64_t>(),
-                                  ticket.as<uint32_t>(), s);
+            onesweep_launch<K, 8, ROLE>(ki, vi, ko, vo, (uint32_t)n, sh, b, status.as<uint64_t>(),
+                                        ticket.as<uint32_t>(), s);
         else
-            onesweep_launch<K, 16>(ki, vi, ko, vo, (uint32_t)n, sh, b, status.as<uint64_t>(),
-                                   ticket.as<uint32_t>(), s);
+            onesweep_launch<K, 16, ROLE>(ki, vi, ko, vo, (uint32_t)n, sh, b, status.as<uint64_t>(),
+                                         ticket.as<uint32_t>(), s);
         inB = !inB;
     }
     // status/ticket are released stream-ordered (or by hipFree, which waits)
@@ -446,7 +451,7 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
         HIPCHK(hipStreamSynchronize(s));
         if (h[passes * kRadix]) fail(DOM_AGG_ENAN, "a coordinate on axis %d is NaN", axis);
         const std::vector<int> shifts = live_shifts(h, passes, n);
-        const bool inB = radix_sort<KP>(kA.as<KP>(), vA.as<uint32_t>(), kB.as<KP>(), vB.as<uint32_t>(), n,
+        const bool inB = radix_sort<KP, 0>(kA.as<KP>(), vA.as<uint32_t>(), kB.as<KP>(), vB.as<uint32_t>(), n,
                                         shifts, bases.as<uint32_t>(), P->tune.point_sort_items, s);
         DevBuf &sk = inB ? kB : kA;
         DevBuf &sv = inB ? vB : vA;
@@ -588,7 +593,7 @@ void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &ou
     if (!P->rec_shifts.empty()) {
         kB.alloc(E * sizeof(K), s);
         vB.alloc(E * 4, s);
-        inB = radix_sort<K>(kA.as<K>(), vA.as<uint32_t>(), kB.as<K>(), vB.as<uint32_t>(), E, P->rec_shifts,
+        inB = radix_sort<K, 1>(kA.as<K>(), vA.as<uint32_t>(), kB.as<K>(), vB.as<uint32_t>(), E, P->rec_shifts,
                             bases.as<uint32_t>(), P->tune.record_sort_items, s);
     }
     outK = std::move(inB ? kB : kA);

@@ -112,8 +112,10 @@ __global__ __launch_bounds__(BLOCK) void hist_kernel(const K *__restrict__ keys,
 //
 // n < 2^32 - 2*TILE.  status: [tiles][256] words, zero before the launch;
 // ticket: zero before the launch.  digit_base: [256] exclusive bases of the
-// pass's digits over the whole array.
-template <class K, int BLOCK, int ITEMS>
+// pass's digits over the whole array.  ROLE only names the instantiation
+// (0: per-point coordinate sorts, 1: the sort of the expanded records) so the
+// two show up separately in profiles.
+template <class K, int BLOCK, int ITEMS, int ROLE = 0>
 __global__ __launch_bounds__(BLOCK) void onesweep_kernel(
     const K *__restrict__ kin, const uint32_t *__restrict__ vin, K *__restrict__ kout,
     uint32_t *__restrict__ vout, uint32_t n, int shift, const uint32_t *__restrict__ digit_base,
