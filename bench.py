@@ -213,6 +213,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="only the headline workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 19)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one 1 GiB elementwise copy first (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
@@ -224,6 +226,12 @@ def main():
     assert torch.cuda.is_available(), "no GPU"
     log(f"device: {torch.cuda.get_device_name(0)}")
 
+    if args.calibrate_copy:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.add(a, 0.0, out=b)  # reads 1 GiB, writes 1 GiB
+        torch.cuda.synchronize()
+        del a, b
     case = workloads.f32_2d_16m()
     log(f"headline: {case.name} m={case.m} |D|={case.D.shape[0]} |Q|={case.Q.shape[0]}")
     T, kern, info, _ = run_plain(case, args.steps, args.warmup)

@@ -103,6 +103,7 @@ typedef struct {
     int32_t digit_bits;    /* radix digit width chosen for the record sort */
     int32_t sort_tile;     /* records per workgroup tile in the record sort */
     int32_t scan_tile;     /* records per workgroup tile in the segmented scans */
+    int32_t regroup_slots; /* level-tuple slots of the regrouping; 0 = atomic F instead */
     size_t workspace_bytes;/* device memory held by the plan */
 } dom_agg_plan_info;
 
@@ -158,9 +159,11 @@ dom_agg_status dom_agg_plan(dom_agg_plan_t *plan, int m, dom_agg_dtype coord_dty
  *   weights  device, [n_data] of weight_dtype in data-row order (NULL for COUNT).
  *   out      device, [n_query] of the output dtype, fully overwritten.
  *
- * Integer results and MAX are exact and deterministic; fp32/fp64 sums are
- * exact up to rounding order (the order of combination can differ between
- * calls).
+ * Integer results and MAX are exact.  fp32/fp64 sums are exact up to
+ * rounding order; that order is fixed (results repeat bit for bit) unless the
+ * plan regroups with atomics (regroup_slots = 0 in dom_agg_plan_info, chosen
+ * when the table of level-tuple slots would be large and sparse, e.g. m = 4
+ * with wide ranks).
  */
 dom_agg_status dom_agg_forward(dom_agg_plan_t plan, dom_agg_op op, dom_agg_dtype weight_dtype,
                                const void *weights, void *out, void *stream);

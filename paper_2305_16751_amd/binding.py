@@ -60,6 +60,7 @@ class PlanInfo(ctypes.Structure):
         ("digit_bits", ctypes.c_int32),
         ("sort_tile", ctypes.c_int32),
         ("scan_tile", ctypes.c_int32),
+        ("regroup_slots", ctypes.c_int32),
         ("workspace_bytes", ctypes.c_size_t),
     ]
 

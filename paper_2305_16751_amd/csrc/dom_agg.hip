@@ -163,12 +163,30 @@ hipEvent_t take_event() {
     return e;
 }
 
+// DOM_AGG_SYNC_CHECK=1: synchronise after every launch and name the kernel in
+// the error, to attribute a device fault (slow; for debugging only).
+bool sync_check() {
+    static const bool on = [] {
+        const char *e = std::getenv("DOM_AGG_SYNC_CHECK");
+        return e && e[0] == '1';
+    }();
+    return on;
+}
+
 template <class F>
 void launch(const char *name, hipStream_t s, F &&f) {
     bool timed;
     {
         std::lock_guard<std::mutex> lk(g_tmu);
         timed = g_timing && !t_capturing;
+    }
+    if (sync_check() && !t_capturing) {
+        f();
+        const hipError_t e1 = hipGetLastError();
+        const hipError_t e2 = hipStreamSynchronize(s);
+        if (e1 != hipSuccess || e2 != hipSuccess)
+            fail(DOM_AGG_EHIP, "kernel %s: %s", name, hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+        return;
     }
     if (!timed) {
         f();
@@ -224,6 +242,10 @@ uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 
 constexpr int kBlock = 256;
 constexpr uint64_t kMaxRecords = (1ull << 32) - (1ull << 20);
+// slot-mode regrouping is used when the level-tuple table is small and dense
+// enough; beyond these, partials are combined with atomics
+constexpr uint64_t kMaxSlots = 1024;
+constexpr uint64_t kMaxSlotBytes = 64ull << 30;
 
 }  // namespace
 
@@ -247,7 +269,13 @@ struct dom_agg_plan_s {
     TuneChoice tune;
 
     // per-point state, in last-axis order
-    DevBuf off, rs, pay, inst_s, ltab;
+    DevBuf off, rs, pay, inst_s;
+    // per-point state by slot, kept for the regrouping: ranks, instance, widths
+    DevBuf rank, inst_of_slot, ltab;
+    // regrouping: level-tuple slots (slot mode) or atomic F
+    uint32_t n_slots = 1;
+    bool use_slots = true;
+    DevBuf part;
     // sorted records (KEEP)
     DevBuf rkeys, rvals;
     // look-back words and ticket of the forward/backward scans
@@ -261,8 +289,19 @@ struct dom_agg_plan_s {
     std::vector<uintptr_t> gkey;
 
     size_t workspace() const {
-        return off.bytes + rs.bytes + pay.bytes + inst_s.bytes + ltab.bytes + rkeys.bytes +
-               rvals.bytes + scan_status.bytes + scan_ticket.bytes + ed_counter.bytes;
+        return off.bytes + rs.bytes + pay.bytes + inst_s.bytes + rank.bytes + inst_of_slot.bytes + ltab.bytes +
+               part.bytes + rkeys.bytes + rvals.bytes + scan_status.bytes + scan_ticket.bytes + ed_counter.bytes;
+    }
+    SlotMap slot_map() const {
+        SlotMap sm{};
+        sm.nax = nax;
+        for (int a = 0; a < 3; ++a) {
+            sm.field_shift[a] = field_shift[a];
+            sm.field_mask[a] = Lmax[a] >= 32 ? 0xffffffffu : ((1u << Lmax[a]) - 1u);
+            sm.radix[a] = (uint32_t)std::max(Lmax[a], 1);
+        }
+        sm.n_slots = nax == 0 ? 1u : n_slots;
+        return sm;
     }
 };
 
@@ -305,38 +344,48 @@ void clear_lookback(uint64_t *status, uint64_t words, uint32_t *ticket, hipStrea
 // Radix sort driver.
 
 template <class K, int ROLE>
-const char *onesweep_name(int items) {
-    if constexpr (ROLE == 1) {
-        if constexpr (sizeof(K) == 4) return items == 8 ? "onesweep_records_u32_t2048" : "onesweep_records_u32_t4096";
-        else return items == 8 ? "onesweep_records_u64_t2048" : "onesweep_records_u64_t4096";
-    } else {
-        if constexpr (sizeof(K) == 4) return items == 8 ? "onesweep_points_u32_t2048" : "onesweep_points_u32_t4096";
-        else return items == 8 ? "onesweep_points_u64_t2048" : "onesweep_points_u64_t4096";
-    }
+const char *onesweep_name(int tile) {
+    static const char *names[2][2][3] = {
+        {{"onesweep_points_u32_t2048", "onesweep_points_u32_t4096", "onesweep_points_u32_t8192"},
+         {"onesweep_points_u64_t2048", "onesweep_points_u64_t4096", "onesweep_points_u64_t8192"}},
+        {{"onesweep_records_u32_t2048", "onesweep_records_u32_t4096", "onesweep_records_u32_t8192"},
+         {"onesweep_records_u64_t2048", "onesweep_records_u64_t4096", "onesweep_records_u64_t8192"}}};
+    const int ti = tile == 2048 ? 0 : tile == 4096 ? 1 : 2;
+    return names[ROLE][sizeof(K) == 8][ti];
 }
 
-template <class K, int ITEMS, int ROLE>
+template <class K, class S, int BLOCK, int ITEMS, int ROLE>
 void onesweep_launch(const K *kin, const uint32_t *vin, K *kout, uint32_t *vout, uint32_t n,
-                     int shift, const uint32_t *bases, uint64_t *status, uint32_t *ticket,
-                     hipStream_t s) {
-    constexpr int TILE = kBlock * ITEMS;
+                     int shift, const uint32_t *bases, S *status, uint32_t *ticket, hipStream_t s) {
+    constexpr int TILE = BLOCK * ITEMS;
     const unsigned tiles = (unsigned)ceil_div(n, TILE);
-    clear_lookback(status, (uint64_t)tiles * kRadix, ticket, s);
-    launch(onesweep_name<K, ROLE>(ITEMS), s, [&] {
-        onesweep_kernel<K, kBlock, ITEMS, ROLE><<<tiles, kBlock, 0, s>>>(kin, vin, kout, vout, n, shift,
-                                                                         bases, status, ticket);
+    clear_lookback(reinterpret_cast<uint64_t *>(status), ceil_div((uint64_t)tiles * kRadix * sizeof(S), 8),
+                   ticket, s);
+    launch(onesweep_name<K, ROLE>(TILE), s, [&] {
+        onesweep_kernel<K, S, BLOCK, ITEMS, ROLE><<<tiles, BLOCK, 0, s>>>(kin, vin, kout, vout, n, shift,
+                                                                          bases, status, ticket);
     });
+}
+
+template <class K, class S, int ROLE>
+void onesweep_dispatch(int tile, const K *kin, const uint32_t *vin, K *kout, uint32_t *vout, uint32_t n,
+                       int shift, const uint32_t *bases, void *status, uint32_t *ticket, hipStream_t s) {
+    S *st = static_cast<S *>(status);
+    if (tile == 2048) onesweep_launch<K, S, 256, 8, ROLE>(kin, vin, kout, vout, n, shift, bases, st, ticket, s);
+    else if (tile == 8192) onesweep_launch<K, S, 512, 16, ROLE>(kin, vin, kout, vout, n, shift, bases, st, ticket, s);
+    else onesweep_launch<K, S, 256, 16, ROLE>(kin, vin, kout, vout, n, shift, bases, st, ticket, s);
 }
 
 // Sorts (kA, vA) by the listed digit shifts; returns true when the result
 // ended up in (kB, vB).  bases: [passes][256] (pass p at shift 8p).
 template <class K, int ROLE>
 bool radix_sort(K *kA, uint32_t *vA, K *kB, uint32_t *vB, uint64_t n, const std::vector<int> &shifts,
-                const uint32_t *bases, int items, hipStream_t s) {
+                const uint32_t *bases, int tile, hipStream_t s) {
     if (n == 0 || shifts.empty()) return false;
-    const int tile = kBlock * (items == 8 ? 8 : 16);
+    if (!valid_sort_tile(tile)) tile = 4096;
+    const bool narrow = n < (1ull << 30);  // every digit count fits 30 bits
     DevBuf status, ticket;
-    status.alloc(ceil_div(n, tile) * kRadix * sizeof(uint64_t), s);
+    status.alloc(ceil_div(n, tile) * kRadix * (narrow ? 4 : 8) + 8, s);
     ticket.alloc(sizeof(uint32_t) * 4, s);
     bool inB = false;
     for (int sh : shifts) {
@@ -345,16 +394,31 @@ bool radix_sort(K *kA, uint32_t *vA, K *kB, uint32_t *vB, uint64_t n, const std:
         K *ko = inB ? kA : kB;
         uint32_t *vo = inB ? vA : vB;
         const uint32_t *b = bases + (sh / kRadixBits) * kRadix;
-        if (items == 8)
-            onesweep_launch<K, 8, ROLE>(ki, vi, ko, vo, (uint32_t)n, sh, b, status.as<uint64_t>(),
-                                        ticket.as<uint32_t>(), s);
+        if (narrow)
+            onesweep_dispatch<K, uint32_t, ROLE>(tile, ki, vi, ko, vo, (uint32_t)n, sh, b, status.p,
+                                                 ticket.as<uint32_t>(), s);
         else
-            onesweep_launch<K, 16, ROLE>(ki, vi, ko, vo, (uint32_t)n, sh, b, status.as<uint64_t>(),
-                                         ticket.as<uint32_t>(), s);
+            onesweep_dispatch<K, uint64_t, ROLE>(tile, ki, vi, ko, vo, (uint32_t)n, sh, b, status.p,
+                                                 ticket.as<uint32_t>(), s);
         inB = !inB;
     }
     // status/ticket are released stream-ordered (or by hipFree, which waits)
     return inB;
+}
+
+// Reduces part[nblocks][passes][256] to counts and exclusive bases [passes][256].
+void reduce_hist(const uint32_t *part, int nblocks, int passes, uint32_t *counts, uint32_t *bases,
+                 hipStream_t s) {
+    const int R = std::max(1, std::min(64, nblocks));
+    const int rows = (nblocks + R - 1) / R;
+    DevBuf part2;
+    part2.alloc((size_t)R * passes * kRadix * 4, s);
+    launch("hist_reduce", s, [&] {
+        hist_partial_kernel<<<dim3(passes, R), kRadix, 0, s>>>(part, nblocks, passes, rows, part2.as<uint32_t>());
+    });
+    launch("hist_reduce", s, [&] {
+        hist_reduce_kernel<<<passes, kRadix, 0, s>>>(part2.as<uint32_t>(), R, passes, counts, bases);
+    });
 }
 
 // Passes whose digit is not the same for every key.
@@ -378,7 +442,7 @@ void scan_launch(const char *name, const Prob &p, uint64_t n, uint64_t *status, 
     if (n == 0) return;
     constexpr int TILE = kBlock * ITEMS;
     const uint64_t tiles = ceil_div(n, TILE);
-    const uint64_t words = tiles * ScanStatusWords<typename Prob::V>::kWords;
+    const uint64_t words = 2 * tiles * ScanStatusWords<typename Prob::V>::kWords;
     if (words > words_cap) fail(DOM_AGG_EHIP, "internal: scan status too small");
     clear_lookback(status, words, ticket, s);
     launch(name, s, [&] {
@@ -396,7 +460,8 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
     const int m = P->m, nax = P->nax;
     const int64_t ni = P->n_inst;
 
-    DevBuf inst_of_slot, doff_dev, qoff_dev;
+    DevBuf &inst_of_slot = P->inst_of_slot;
+    DevBuf doff_dev, qoff_dev;
     if (P->batched) {
         doff_dev.alloc((ni + 1) * sizeof(int64_t), s);
         qoff_dev.alloc((ni + 1) * sizeof(int64_t), s);
@@ -409,7 +474,8 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
         });
     }
 
-    DevBuf kA, kB, vA, vB, rank, kcount, nanflag, part, counts, bases;
+    DevBuf &rank = P->rank;
+    DevBuf kA, kB, vA, vB, kcount, nanflag, part, counts, bases;
     kA.alloc((size_t)n * sizeof(KP), s);
     kB.alloc((size_t)n * sizeof(KP), s);
     vA.alloc((size_t)n * 4, s);
@@ -430,7 +496,7 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
     bases.alloc((size_t)passes * kRadix * 4, s);
 
     DevBuf scan_status, scan_ticket;
-    scan_status.alloc((ceil_div(n, kBlock * 8) + 1) * sizeof(uint64_t) * 2, s);
+    scan_status.alloc((ceil_div(n, kBlock * 8) + 1) * sizeof(uint64_t) * 4, s);
     scan_ticket.alloc(16, s);
 
     // expanded axes first, the real (last) axis last
@@ -440,10 +506,7 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
                 qq, dq, m, axis, nQ, n, inst_of_slot.as<uint32_t>(), kA.as<KP>(), vA.as<uint32_t>(),
                 passes, part.as<uint32_t>(), nanflag.as<uint32_t>());
         });
-        launch("hist_reduce", s, [&] {
-            hist_reduce_kernel<<<passes, kRadix, 0, s>>>(part.as<uint32_t>(), (int)ext_blocks, passes,
-                                                         counts.as<uint32_t>(), bases.as<uint32_t>());
-        });
+        reduce_hist(part.as<uint32_t>(), (int)ext_blocks, passes, counts.as<uint32_t>(), bases.as<uint32_t>(), s);
         const size_t cb = (size_t)passes * kRadix * 4;
         uint32_t *h = static_cast<uint32_t *>(hs.get(cb + 4));
         HIPCHK(hipMemcpyAsync(h, counts.p, cb, hipMemcpyDeviceToHost, s));
@@ -452,7 +515,7 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
         if (h[passes * kRadix]) fail(DOM_AGG_ENAN, "a coordinate on axis %d is NaN", axis);
         const std::vector<int> shifts = live_shifts(h, passes, n);
         const bool inB = radix_sort<KP, 0>(kA.as<KP>(), vA.as<uint32_t>(), kB.as<KP>(), vB.as<uint32_t>(), n,
-                                        shifts, bases.as<uint32_t>(), P->tune.point_sort_items, s);
+                                        shifts, bases.as<uint32_t>(), P->tune.point_sort_tile, s);
         DevBuf &sk = inB ? kB : kA;
         DevBuf &sv = inB ? vB : vA;
         if (axis < nax) {
@@ -492,6 +555,13 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
     P->key_bits = sum + (P->batched ? P->inst_bits : 0);
     if (P->key_bits > 64) fail(DOM_AGG_ETOOBIG, "record sort key needs %d bits (> 64)", P->key_bits);
     P->key64 = P->key_bits > 32;
+    {
+        uint64_t S = 1;
+        for (int a = 0; a < nax; ++a) S *= (uint64_t)std::max(P->Lmax[a], 1);
+        const uint64_t rows = (uint64_t)std::max(P->nQ, P->nD);
+        P->use_slots = S <= kMaxSlots && S * rows * 8 <= kMaxSlotBytes;
+        P->n_slots = (uint32_t)std::min<uint64_t>(S, 0xffffffffu);
+    }
 
     if (nax) {
         P->ltab.alloc(lt.size(), s);
@@ -539,9 +609,19 @@ void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &ou
     kA.alloc(E * sizeof(K), s);
     vA.alloc(E * 4, s);
     const int passes = std::max(1, (int)ceil_div(P->key_bits, kRadixBits));
-    constexpr int EITEMS = 16;
+    constexpr int EITEMS = 8;
     constexpr int CHUNK = kBlock * EITEMS;
-    const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(ceil_div(E, CHUNK), 2048));
+    constexpr int CHUNK_SHIFT = 11;
+    static_assert((1 << CHUNK_SHIFT) == CHUNK, "");
+    const uint64_t nchunks = ceil_div(E, CHUNK);
+    const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(nchunks, 4096));
+    DevBuf chunk_k;
+    chunk_k.alloc(nchunks * 4, s);
+    launch("chunk_start", s, [&] {
+        const unsigned g = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(ceil_div(P->n, kBlock), 4096));
+        chunk_start_kernel<<<g, kBlock, 0, s>>>(P->off.as<uint64_t>(), (uint32_t)P->n, CHUNK_SHIFT,
+                                                chunk_k.as<uint32_t>());
+    });
     part.alloc((size_t)grid * passes * kRadix * 4, s);
     counts.alloc((size_t)passes * kRadix * 4, s);
     bases.alloc((size_t)passes * kRadix * 4, s);
@@ -554,6 +634,7 @@ void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &ou
     a.pay = P->pay.as<uint32_t>();
     a.inst_s = P->inst_s.as<uint32_t>();
     a.ltab = P->ltab.as<uint8_t>();
+    a.chunk_k = chunk_k.as<uint32_t>();
     a.n = (uint32_t)P->n;
     a.n_inst = (uint32_t)P->n_inst;
     a.E = E;
@@ -574,10 +655,7 @@ void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &ou
         case 2: emit(std::integral_constant<int, 2>{}); break;
         default: emit(std::integral_constant<int, 3>{}); break;
     }
-    launch("hist_reduce", s, [&] {
-        hist_reduce_kernel<<<passes, kRadix, 0, s>>>(part.as<uint32_t>(), (int)grid, passes,
-                                                     counts.as<uint32_t>(), bases.as<uint32_t>());
-    });
+    reduce_hist(part.as<uint32_t>(), (int)grid, passes, counts.as<uint32_t>(), bases.as<uint32_t>(), s);
     if (probe) {
         const size_t cb = (size_t)passes * kRadix * 4;
         uint32_t *h = static_cast<uint32_t *>(hs->get(cb + 8));
@@ -594,7 +672,7 @@ void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &ou
         kB.alloc(E * sizeof(K), s);
         vB.alloc(E * 4, s);
         inB = radix_sort<K, 1>(kA.as<K>(), vA.as<uint32_t>(), kB.as<K>(), vB.as<uint32_t>(), E, P->rec_shifts,
-                            bases.as<uint32_t>(), P->tune.record_sort_items, s);
+                            bases.as<uint32_t>(), P->tune.record_sort_tile, s);
     }
     outK = std::move(inB ? kB : kA);
     outV = std::move(inB ? vB : vA);
@@ -615,18 +693,70 @@ void records_for_call(Plan *P, hipStream_t s, DevBuf &k, DevBuf &v, const void *
 // ---------------------------------------------------------------------------
 // Forward and backward.
 
+RegroupArgs regroup_args(const Plan *P, bool queries) {
+    RegroupArgs r{};
+    r.rank = P->rank.as<uint32_t>();
+    r.inst_of_slot = P->inst_of_slot.as<uint32_t>();
+    r.ltab = P->ltab.as<uint8_t>();
+    r.n = (uint32_t)P->n;
+    r.n_inst = (uint32_t)P->n_inst;
+    r.slot_base = queries ? 0u : (uint32_t)P->nQ;
+    r.digit = queries ? 1u : 0u;
+    const SlotMap sm = P->slot_map();
+    for (int a = 0; a < 3; ++a) r.radix[a] = sm.radix[a];
+    r.nout = (uint64_t)(queries ? P->nQ : P->nD);
+    return r;
+}
+
+template <class V, int OP>
+void regroup(const Plan *P, bool queries, const V *part, V *out, hipStream_t s) {
+    const RegroupArgs ra = regroup_args(P, queries);
+    const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(ceil_div(ra.nout, kBlock), 8192));
+    auto go = [&](auto nax_c) {
+        constexpr int NAX = decltype(nax_c)::value;
+        launch("regroup", s, [&] { regroup_kernel<V, OP, NAX><<<grid, kBlock, 0, s>>>(ra, part, out); });
+    };
+    switch (P->nax) {
+        case 0: go(std::integral_constant<int, 0>{}); break;
+        case 1: go(std::integral_constant<int, 1>{}); break;
+        case 2: go(std::integral_constant<int, 2>{}); break;
+        default: go(std::integral_constant<int, 3>{}); break;
+    }
+}
+
+template <class V, int OP>
+V host_identity() {
+    if constexpr (OP == OP_MAX) {
+        if constexpr (std::is_floating_point<V>::value) return -std::numeric_limits<V>::infinity();
+        else return std::numeric_limits<V>::min();
+    } else {
+        return V(0);
+    }
+}
+
+// The slot table of the regrouping, sized before any graph capture.
+void ensure_part(Plan *P, size_t vbytes, hipStream_t s) {
+    if (!P->use_slots || P->nax == 0) return;
+    const size_t need = (size_t)P->n_slots * (size_t)std::max(P->nQ, P->nD) * vbytes;
+    if (P->part.bytes < need) P->part.alloc(need, s);
+}
+
 template <class K, class W, class V, int OP>
 void forward_typed(Plan *P, const void *kp, const uint32_t *vp, const void *w, void *out, hipStream_t s) {
-    ForwardProblem<K, W, V, OP> fp{static_cast<const K *>(kp), vp, static_cast<const W *>(w),
-                                   static_cast<V *>(out)};
-    V e;
-    if constexpr (OP == OP_MAX) {
-        if constexpr (std::is_floating_point<V>::value) e = -std::numeric_limits<V>::infinity();
-        else e = std::numeric_limits<V>::min();
+    ForwardProblem<K, W, V, OP> fp{};
+    fp.keys = static_cast<const K *>(kp);
+    fp.vals = vp;
+    fp.w = static_cast<const W *>(w);
+    fp.out = static_cast<V *>(out);
+    fp.sm = P->slot_map();
+    fp.stride = (uint64_t)P->nQ;
+    if (P->use_slots) {
+        // m = 1: every query has exactly one record, so it is stored in place
+        fp.part = P->nax == 0 ? static_cast<V *>(out) : P->part.as<V>();
     } else {
-        e = V(0);
+        fp.part = nullptr;
+        fill(static_cast<V *>(out), (uint64_t)P->nQ, host_identity<V, OP>(), s);
     }
-    fill(static_cast<V *>(out), (uint64_t)P->nQ, e, s);
     if (P->tune.scan_items == 8 || sizeof(K) == 8)
         scan_launch<ForwardProblem<K, W, V, OP>, 8>("forward_scan", fp, (uint64_t)P->E,
                                                     P->scan_status.as<uint64_t>(), P->scan_words,
@@ -635,6 +765,7 @@ void forward_typed(Plan *P, const void *kp, const uint32_t *vp, const void *w, v
         scan_launch<ForwardProblem<K, W, V, OP>, 16>("forward_scan", fp, (uint64_t)P->E,
                                                      P->scan_status.as<uint64_t>(), P->scan_words,
                                                      P->scan_ticket.as<uint32_t>(), s);
+    if (P->use_slots && P->nax > 0) regroup<V, OP>(P, true, P->part.as<V>(), static_cast<V *>(out), s);
 }
 
 template <class K>
@@ -660,15 +791,27 @@ void forward_dispatch(Plan *P, dom_agg_op op, dom_agg_dtype wdt, const void *kp,
 
 template <class K, class G>
 void backward_typed(Plan *P, const void *kp, const uint32_t *vp, const void *g, void *grad, hipStream_t s) {
-    BackwardProblem<K, G> bp{static_cast<const K *>(kp), vp, static_cast<const G *>(g), static_cast<G *>(grad),
-                             (uint64_t)P->E};
-    fill(static_cast<G *>(grad), (uint64_t)P->nD, G(0), s);
+    BackwardProblem<K, G> bp{};
+    bp.keys = static_cast<const K *>(kp);
+    bp.vals = vp;
+    bp.g = static_cast<const G *>(g);
+    bp.grad = static_cast<G *>(grad);
+    bp.sm = P->slot_map();
+    bp.stride = (uint64_t)P->nD;
+    bp.E = (uint64_t)P->E;
+    if (P->use_slots) {
+        bp.part = P->nax == 0 ? static_cast<G *>(grad) : P->part.as<G>();
+    } else {
+        bp.part = nullptr;
+        fill(static_cast<G *>(grad), (uint64_t)P->nD, G(0), s);
+    }
     if (P->tune.scan_items == 8 || sizeof(K) == 8)
         scan_launch<BackwardProblem<K, G>, 8>("backward_scan", bp, (uint64_t)P->E, P->scan_status.as<uint64_t>(),
                                               P->scan_words, P->scan_ticket.as<uint32_t>(), s);
     else
         scan_launch<BackwardProblem<K, G>, 16>("backward_scan", bp, (uint64_t)P->E, P->scan_status.as<uint64_t>(),
                                                P->scan_words, P->scan_ticket.as<uint32_t>(), s);
+    if (P->use_slots && P->nax > 0) regroup<G, OP_SUM>(P, false, P->part.as<G>(), static_cast<G *>(grad), s);
 }
 
 // Runs `body` directly, or through the plan's HIP graph in DOM_AGG_GRAPH mode.
@@ -736,15 +879,15 @@ void tune_plan(Plan *P, hipStream_t s) {
     const TuneKey key{P->m, P->key_bits, bits_for((uint64_t)P->E)};
     TuneChoice c;
     if (tc.lookup(key, &c)) {
-        P->tune.record_sort_items = c.record_sort_items;
+        P->tune.record_sort_tile = c.record_sort_tile;
         P->tune.scan_items = c.scan_items;
         return;
     }
     // the per-point state is still present here (plan construction)
     float best = 1e30f;
-    int best_items = P->tune.record_sort_items;
-    for (int items : {8, 16}) {
-        P->tune.record_sort_items = items;
+    int best_tile = P->tune.record_sort_tile;
+    for (int tile : {2048, 4096, 8192}) {
+        P->tune.record_sort_tile = tile;
         DevBuf k, v;
         const float ms = time_ms(s, [&] {
             if (P->key64) build_records<uint64_t>(P, s, nullptr, false, k, v);
@@ -752,11 +895,12 @@ void tune_plan(Plan *P, hipStream_t s) {
         });
         if (ms < best) {
             best = ms;
-            best_items = items;
+            best_tile = tile;
         }
     }
-    P->tune.record_sort_items = best_items;
+    P->tune.record_sort_tile = best_tile;
     if (!P->key64 && P->rkeys.p && P->nQ > 0) {
+        ensure_part(P, 8, s);
         DevBuf out;
         out.alloc((size_t)P->nQ * 8, s);
         best = 1e30f;
@@ -873,7 +1017,7 @@ dom_agg_status dom_agg_plan(dom_agg_plan_t *plan, int m, dom_agg_dtype coord_dty
             sig_keys.reset();
             sig_slots.reset();
             const uint64_t tiles = ceil_div((uint64_t)std::max<int64_t>(P->E, 1), kBlock * 8);
-            P->scan_words = tiles * 2;
+            P->scan_words = tiles * 4;
             P->scan_status.alloc(P->scan_words * 8, s);
             P->scan_ticket.alloc(16, s);
             if (P->E > 0) {
@@ -887,12 +1031,11 @@ dom_agg_status dom_agg_plan(dom_agg_plan_t *plan, int m, dom_agg_dtype coord_dty
                     P->rkeys.reset();
                     P->rvals.reset();
                 } else {
-                    // the per-point state is only needed to rebuild the records
+                    // the last-axis-ordered state is only needed to rebuild the records
                     P->rs.reset();
                     P->pay.reset();
                     P->inst_s.reset();
                     P->off.reset();
-                    P->ltab.reset();
                 }
             }
             HIPCHK(hipStreamSynchronize(s));
@@ -916,6 +1059,9 @@ dom_agg_status dom_agg_forward(dom_agg_plan_t plan, dom_agg_op op, dom_agg_dtype
         require_gfx950(&dev);
         if (dev != plan->device) fail(DOM_AGG_EINVAL, "plan belongs to device %d, current is %d", plan->device, dev);
         hipStream_t s = static_cast<hipStream_t>(stream);
+        const bool wide = op == DOM_AGG_COUNT || (op == DOM_AGG_SUM && weight_dtype != DOM_AGG_F32) ||
+                          weight_dtype == DOM_AGG_I64 || weight_dtype == DOM_AGG_F64;
+        ensure_part(plan, wide ? 8 : 4, s);
         const std::vector<uintptr_t> key{1, (uintptr_t)op, (uintptr_t)weight_dtype, (uintptr_t)weights,
                                          (uintptr_t)out};
         maybe_graph(plan, key, s, [&](hipStream_t cs) {
@@ -944,6 +1090,7 @@ dom_agg_status dom_agg_backward(dom_agg_plan_t plan, dom_agg_dtype grad_dtype, c
         require_gfx950(&dev);
         if (dev != plan->device) fail(DOM_AGG_EINVAL, "plan belongs to device %d, current is %d", plan->device, dev);
         hipStream_t s = static_cast<hipStream_t>(stream);
+        ensure_part(plan, grad_dtype == DOM_AGG_F64 ? 8 : 4, s);
         const std::vector<uintptr_t> key{2, (uintptr_t)grad_dtype, (uintptr_t)grad_out, (uintptr_t)grad_weights};
         maybe_graph(plan, key, s, [&](hipStream_t cs) {
             DevBuf k, v;
@@ -975,8 +1122,9 @@ dom_agg_status dom_agg_plan_get_info(dom_agg_plan_t plan, dom_agg_plan_info *inf
         for (int a = 0; a < 3; ++a) info->L[a] = plan->Lmax[a];
         info->sort_passes = (int32_t)plan->rec_shifts.size();
         info->digit_bits = kRadixBits;
-        info->sort_tile = kBlock * plan->tune.record_sort_items;
+        info->sort_tile = plan->tune.record_sort_tile;
         info->scan_tile = kBlock * ((plan->tune.scan_items == 8 || plan->key64) ? 8 : 16);
+        info->regroup_slots = plan->use_slots ? (int32_t)plan->n_slots : 0;
         info->workspace_bytes = plan->workspace();
     });
 }

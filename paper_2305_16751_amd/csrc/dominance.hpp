@@ -201,11 +201,12 @@ struct CountProblem {
 // order inside every segment.
 
 struct EmitArgs {
-    const uint64_t *off;     // [n + 1]
-    const uint32_t *rs;      // [NAX][n]
-    const uint32_t *pay;     // [n]
-    const uint32_t *inst_s;  // [n] or null
-    const uint8_t *ltab;     // [NAX][n_inst]
+    const uint64_t *off;      // [n + 1]
+    const uint32_t *rs;       // [NAX][n]
+    const uint32_t *pay;      // [n]
+    const uint32_t *inst_s;   // [n] or null
+    const uint8_t *ltab;      // [NAX][n_inst]
+    const uint32_t *chunk_k;  // [chunks]: the point holding each chunk's first record
     uint32_t n, n_inst;
     uint64_t E;
     int field_shift[3];
@@ -215,101 +216,205 @@ struct EmitArgs {
     unsigned long long *data_records;
 };
 
-// the t-th set digit of the L-digit string x counted from its most
-// significant digit; returns its position from the top (0-based)
-__device__ __forceinline__ uint32_t select_from_top(uint32_t x, uint32_t L, uint32_t t) {
-    uint32_t y = __brev(x) >> (32u - L);
-    for (uint32_t i = 0; i < t; ++i) y &= y - 1u;
-    return (uint32_t)(__ffs(y) - 1);
+// chunk_k[c] = the point k with off[k] <= c * chunk < off[k+1].
+__global__ void chunk_start_kernel(const uint64_t *__restrict__ off, uint32_t n, int chunk_shift,
+                                   uint32_t *__restrict__ chunk_k) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+        const uint64_t lo = off[k], hi = off[k + 1];
+        const uint64_t mask = (1ull << chunk_shift) - 1;
+        for (uint64_t c = (lo + mask) >> chunk_shift; (c << chunk_shift) < hi; ++c) chunk_k[c] = (uint32_t)k;
+    }
 }
 
+// Per-point state of the walk, cached in LDS for the points of one chunk.
+template <int NAX>
+struct PointCache {
+    static constexpr int kCap = 512;
+    uint32_t off[kCap + 1];  // record offsets relative to the chunk's first point
+    uint32_t pay[kCap];
+    uint32_t inst[kCap];
+    uint32_t rank[NAX > 0 ? NAX : 1][kCap];
+};
+
+// Per-point walk over the product of prefix sets.  For each expanded axis
+// the remaining digits to visit are kept as a mask over the L-digit rank
+// string (bit L-1-j is digit j counted from the top); the last axis moves
+// fastest, like the offsets of the count pass.
+template <int NAX>
+struct PointWalk {
+    uint32_t r[3], L[3], full[3], rem[3];
+    uint32_t payload, inst;
+    bool isq;
+
+    __device__ void set(const EmitArgs &a, uint32_t pay, uint32_t ins, const uint32_t *ranks) {
+        payload = pay;
+        isq = (payload & kQueryFlag) != 0u;
+        inst = ins;
+#pragma unroll
+        for (int ax = 0; ax < NAX; ++ax) {
+            r[ax] = ranks[ax];
+            L[ax] = a.ltab[(uint64_t)ax * a.n_inst + inst];
+            const uint32_t mask = (L[ax] >= 32u) ? 0xffffffffu : ((1u << L[ax]) - 1u);
+            full[ax] = isq ? (r[ax] & mask) : (~r[ax] & mask);
+            rem[ax] = full[ax];
+        }
+    }
+    // point k of the chunk (index idx among its points), from the LDS cache or global memory
+    __device__ void load(const EmitArgs &a, const PointCache<NAX> *pc, bool cached, uint32_t klo, uint32_t idx) {
+        uint32_t rk[3] = {0, 0, 0};
+        uint32_t pay, ins;
+        if (cached) {
+            pay = pc->pay[idx];
+            ins = pc->inst[idx];
+#pragma unroll
+            for (int ax = 0; ax < NAX; ++ax) rk[ax] = pc->rank[ax][idx];
+        } else {
+            const uint32_t k = klo + idx;
+            pay = a.pay[k];
+            ins = a.inst_s ? a.inst_s[k] : 0u;
+#pragma unroll
+            for (int ax = 0; ax < NAX; ++ax) rk[ax] = a.rs[(uint64_t)ax * a.n + k];
+        }
+        set(a, pay, ins, rk);
+    }
+    // positions the walk at the point's t-th record
+    __device__ void seek(uint32_t t) {
+#pragma unroll
+        for (int ax = NAX - 1; ax >= 0; --ax) {
+            const uint32_t c = (uint32_t)__popc(full[ax]);
+            uint32_t ta = t;
+            if (ax > 0) {
+                ta = t % c;
+                t /= c;
+            }
+            for (uint32_t i = 0; i < ta; ++i) rem[ax] &= ~(1u << (31u - __clz(rem[ax])));
+        }
+    }
+    template <class K>
+    __device__ K key(int inst_shift, bool with_inst, const int *field_shift) const {
+        K key = with_inst ? ((K)inst << inst_shift) : K(0);
+#pragma unroll
+        for (int ax = 0; ax < NAX; ++ax) {
+            const uint32_t top = 31u - (uint32_t)__clz(rem[ax]);  // highest remaining digit
+            const uint32_t j = L[ax] - 1u - top;                 // its position from the top
+            const uint32_t node = (1u << j) | (j ? (r[ax] >> (L[ax] - j)) : 0u);
+            key |= (K)node << field_shift[ax];
+        }
+        return key;
+    }
+    // advances to the next record; returns false when the point is exhausted
+    __device__ bool next() {
+#pragma unroll
+        for (int ax = NAX - 1; ax >= 0; --ax) {
+            rem[ax] &= ~(1u << (31u - __clz(rem[ax])));
+            if (rem[ax]) return true;
+            rem[ax] = full[ax];
+        }
+        return false;
+    }
+};
+
+// The flat map (Sec. 4 with Sec. 5).  Record o belongs to the point k with
+// off[k] <= o < off[k+1]; its index t = o - off[k] enumerates the product of
+// the point's per-axis prefix sets, last expanded axis fastest.  On axis a
+// the t_a-th element of P0 (data) or P1 (query) of the L_a-digit rank r is
+// the prefix of length j, j being the position from the top of the t_a-th 0
+// (data) or 1 (query) digit of r; it is stored as the tree node id
+// (1 << j) | (first j digits of r), unique across lengths.  Points come in
+// last-axis order and the record sort is stable, which yields the Sec. 5
+// order inside every segment.
+//
+// A block takes a chunk of CHUNK consecutive records; the state of the
+// chunk's points is loaded into LDS with coalesced reads; each thread then
+// produces ITEMS consecutive records (one search for its first, then a walk),
+// stages keys and payloads in LDS, and the block writes them out coalesced.
+// The radix histogram of every pass is accumulated on the way.
 template <class K, int NAX, int BLOCK, int ITEMS>
 __global__ __launch_bounds__(BLOCK) void emit_kernel(EmitArgs a, K *__restrict__ keys_out,
                                                      uint32_t *__restrict__ vals_out) {
     constexpr int CHUNK = BLOCK * ITEMS;
-    __shared__ uint32_t s_off[CHUNK + 1];
+    using PC = PointCache<NAX>;
+    __shared__ PC s_pc;
+    __shared__ K s_keys[CHUNK];
+    __shared__ uint32_t s_pay[CHUNK];
     __shared__ uint32_t s_hist[kMaxPasses * kRadix];
-    __shared__ uint32_t s_klo, s_khi;
     __shared__ unsigned long long s_data;
     for (int i = threadIdx.x; i < a.passes * kRadix; i += BLOCK) s_hist[i] = 0;
     if (threadIdx.x == 0) s_data = 0;
     uint32_t my_data = 0;
+    const bool with_inst = a.inst_s != nullptr;
+    // the two most significant digits of the node keys are skewed toward 0
+    const int peel_from = a.passes > 2 ? a.passes - 2 : 0;
 
     const uint64_t nchunks = (a.E + CHUNK - 1) / CHUNK;
     for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
         const uint64_t o0 = c * CHUNK;
         const uint64_t o1 = (o0 + CHUNK < a.E) ? o0 + CHUNK : a.E;
-        __syncthreads();
-        if (threadIdx.x < 2) {
-            // largest k with off[k] <= target
-            const uint64_t target = threadIdx.x == 0 ? o0 : o1 - 1;
-            uint32_t lo = 0, hi = a.n;  // off[lo] <= target < off[hi]
-            while (hi - lo > 1) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (a.off[mid] <= target) lo = mid; else hi = mid;
+        const uint32_t klo = a.chunk_k[c];
+        const uint32_t khi = (c + 1 < nchunks) ? a.chunk_k[c + 1] : a.n - 1;  // may be one past
+        const uint32_t npts = khi - klo + 1;
+        const bool cached = npts <= (uint32_t)PC::kCap;
+        const uint64_t obase = a.off[klo];
+        __syncthreads();  // previous chunk done with LDS
+        if (cached) {
+            for (uint32_t i = threadIdx.x; i <= npts; i += BLOCK) s_pc.off[i] = (uint32_t)(a.off[klo + i] - obase);
+            for (uint32_t i = threadIdx.x; i < npts; i += BLOCK) {
+                s_pc.pay[i] = a.pay[klo + i];
+                s_pc.inst[i] = with_inst ? a.inst_s[klo + i] : 0u;
+#pragma unroll
+                for (int ax = 0; ax < NAX; ++ax) s_pc.rank[ax][i] = a.rs[(uint64_t)ax * a.n + klo + i];
             }
-            if (threadIdx.x == 0) s_klo = lo; else s_khi = lo;
         }
         __syncthreads();
-        const uint32_t klo = s_klo, khi = s_khi;
-        const uint32_t npts = khi - klo + 1;
-        const bool cached = npts <= (uint32_t)CHUNK;
-        const uint64_t obase = a.off[klo];
-        if (cached)
-            for (uint32_t i = threadIdx.x; i < npts; i += BLOCK) s_off[i] = (uint32_t)(a.off[klo + i] - obase);
-        __syncthreads();
+        auto offr = [&](uint32_t i) -> uint32_t {
+            return cached ? s_pc.off[i] : (uint32_t)(a.off[klo + i] - obase);
+        };
 
-        uint32_t lo_hint = 0;
+        const uint64_t r0 = o0 + (uint64_t)threadIdx.x * ITEMS;
+        PointWalk<NAX> pw;
+        uint32_t idx = 0, left = 0;
+        if (r0 < o1) {
+            const uint32_t rel = (uint32_t)(r0 - obase);
+            uint32_t lo = 0, hi = npts;  // offr(lo) <= rel < offr(hi)
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (offr(mid) <= rel) lo = mid; else hi = mid;
+            }
+            idx = lo;
+            pw.load(a, &s_pc, cached, klo, idx);
+            const uint32_t t = rel - offr(idx);
+            left = offr(idx + 1) - offr(idx) - t;  // records left in this point
+            pw.seek(t);
+        }
 #pragma unroll 1
         for (int j = 0; j < ITEMS; ++j) {
-            const uint64_t o = o0 + (uint64_t)j * BLOCK + threadIdx.x;
-            const bool valid = o < o1;
+            const bool valid = r0 + j < o1;
             K key = 0;
             if (valid) {
-                const uint32_t rel = (uint32_t)(o - obase);
-                uint32_t lo = lo_hint, hi = npts;  // (relative) off[lo] <= rel < off[hi]
-                if (cached) {
-                    while (hi - lo > 1) {
-                        const uint32_t mid = (lo + hi) >> 1;
-                        if (s_off[mid] <= rel) lo = mid; else hi = mid;
-                    }
-                } else {
-                    while (hi - lo > 1) {
-                        const uint32_t mid = (lo + hi) >> 1;
-                        if (a.off[klo + mid] - obase <= rel) lo = mid; else hi = mid;
-                    }
+                key = pw.template key<K>(a.inst_shift, with_inst, a.field_shift);
+                s_keys[threadIdx.x * ITEMS + j] = key;
+                s_pay[threadIdx.x * ITEMS + j] = pw.payload;
+                my_data += pw.isq ? 0u : 1u;
+                if (--left) {
+                    pw.next();
+                } else if (r0 + j + 1 < o1) {
+                    // next point with records (points without records have equal offsets)
+                    do {
+                        ++idx;
+                        left = offr(idx + 1) - offr(idx);
+                    } while (left == 0);
+                    pw.load(a, &s_pc, cached, klo, idx);
                 }
-                lo_hint = lo;
-                const uint32_t k = klo + lo;
-                uint32_t t = rel - (cached ? s_off[lo] : (uint32_t)(a.off[k] - obase));
-                const uint32_t p = a.pay[k];
-                const bool isq = (p & kQueryFlag) != 0u;
-                const uint32_t ins = a.inst_s ? a.inst_s[k] : 0u;
-                if (a.inst_s) key = (K)ins << a.inst_shift;
-#pragma unroll
-                for (int ax = NAX - 1; ax >= 0; --ax) {
-                    const uint32_t r = a.rs[(uint64_t)ax * a.n + k];
-                    const uint32_t L = a.ltab[(uint64_t)ax * a.n_inst + ins];
-                    const uint32_t pc = (uint32_t)__popc(r);
-                    const uint32_t cnt = isq ? pc : (L - pc);
-                    uint32_t ta;
-                    if (ax == 0) {
-                        ta = t;
-                    } else {
-                        ta = t % cnt;
-                        t /= cnt;
-                    }
-                    const uint32_t mask = (L >= 32u) ? 0xffffffffu : ((1u << L) - 1u);
-                    const uint32_t x = isq ? r : (~r & mask);
-                    const uint32_t jlev = select_from_top(x, L, ta);
-                    const uint32_t node = (1u << jlev) | (jlev ? (r >> (L - jlev)) : 0u);
-                    key |= (K)node << a.field_shift[ax];
-                }
-                keys_out[o] = key;
-                vals_out[o] = p;
-                my_data += isq ? 0u : 1u;
             }
-            hist_add(s_hist, key, valid, a.passes);
+            hist_add(s_hist, key, valid, a.passes, peel_from);
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < CHUNK; i += BLOCK) {
+            if (o0 + i < o1) {
+                keys_out[o0 + i] = s_keys[i];
+                vals_out[o0 + i] = s_pay[i];
+            }
         }
     }
     __syncthreads();
@@ -320,12 +425,34 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(EmitArgs a, K *__restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Forward: the segmented scan of the weights over the sorted records.
-// Segments are runs of equal keys (the bitstring tuple, Sec. 5).  Queries
-// carry the unit e; at a query record the scan value is F over the data
-// records before it in its segment, i.e. over the data points that share
-// this tuple and lie strictly below it on the last axis.  Those partials are
-// then F-reduced into out[query] (the regrouping by ID).
+// Regrouping (Sec. 4: the sort by ID and the scan tagged by ID).  A record's
+// slot is its tuple of tree levels (j_1, ..., j_{m-1}), read off the key (the
+// level of node (1 << j) | prefix is its highest set bit), in mixed radix over
+// the per-axis field widths.  A query has at most one record per slot, and
+// one exactly when every j_a is a 1-digit of its axis-a rank (a 0-digit for
+// data).  So the scan can store each partial at part[slot][row] with a plain
+// store, and a second pass folds each row's valid slots in slot order -- no
+// atomics, and the same fold order on every run.
+
+struct SlotMap {
+    int nax;
+    int field_shift[3];
+    uint32_t field_mask[3];
+    uint32_t radix[3];
+    uint32_t n_slots;  // product of the radices; stores to slots beyond it are dropped
+    template <class K>
+    __device__ __forceinline__ uint32_t slot(K key) const {
+        uint32_t sl = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (a < nax) {
+                const uint32_t node = (uint32_t)(key >> field_shift[a]) & field_mask[a];
+                sl = sl * radix[a] + (31u - (uint32_t)__clz(node));
+            }
+        }
+        return sl;
+    }
+};
 
 enum { OP_SUM = 0, OP_MAX = 1, OP_COUNT = 2 };
 
@@ -336,6 +463,25 @@ template <> __device__ __forceinline__ int64_t lowest<int64_t>() { return INT64_
 template <> __device__ __forceinline__ float lowest<float>() { return -__builtin_inff(); }
 template <> __device__ __forceinline__ double lowest<double>() { return -__builtin_inf(); }
 
+template <class V, int OP>
+struct Monoid {
+    __device__ static V identity() {
+        if constexpr (OP == OP_MAX) return lowest<V>();
+        else return V(0);
+    }
+    __device__ static V combine(V a, V b) {
+        if constexpr (OP == OP_MAX) return b > a ? b : a;
+        else return a + b;
+    }
+};
+
+// Forward: the segmented scan of the weights over the sorted records.
+// Segments are runs of equal keys (the bitstring tuple, Sec. 5).  Queries
+// carry the unit e; at a query record the scan value is F over the data
+// records before it in its segment, i.e. over the data points that share
+// this tuple and lie strictly below it on the last axis.  Each such partial
+// goes to part[slot * nQ + query] (slot mode) or is F-combined atomically
+// into out[query] (atomic mode, for very sparse slot tables).
 template <class K, class W, class Acc, int OP>
 struct ForwardProblem {
     using V = Acc;
@@ -346,16 +492,13 @@ struct ForwardProblem {
     const K *keys;
     const uint32_t *vals;
     const W *w;  // unused for COUNT
-    V *out;
+    V *out;      // atomic mode target
+    V *part;     // slot mode target, or null
+    uint64_t stride;
+    SlotMap sm;
 
-    __device__ V identity() const {
-        if constexpr (OP == OP_MAX) return lowest<V>();
-        else return V(0);
-    }
-    __device__ V combine(V a, V b) const {
-        if constexpr (OP == OP_MAX) return b > a ? b : a;
-        else return a + b;
-    }
+    __device__ V identity() const { return Monoid<V, OP>::identity(); }
+    __device__ V combine(V a, V b) const { return Monoid<V, OP>::combine(a, b); }
     __device__ Raw load(uint64_t i) const { return Raw{keys[i], vals[i]}; }
     __device__ bool head(const Raw &prev, const Raw &cur) const { return prev.key != cur.key; }
     __device__ V value(const Raw &, bool, const Raw &cur, uint64_t) const {
@@ -364,10 +507,14 @@ struct ForwardProblem {
         else return V(w[cur.payload]);
     }
     __device__ void emit(uint64_t, const Raw &cur, V, V, V incl, bool) const {
-        if ((cur.payload & kQueryFlag) && incl != identity()) {
-            V *dst = out + (cur.payload & ~kQueryFlag);
-            if constexpr (OP == OP_MAX) atomic_max(dst, incl);
-            else atomic_sum(dst, incl);
+        if (!(cur.payload & kQueryFlag)) return;
+        const uint32_t q = cur.payload & ~kQueryFlag;
+        if (part) {
+            const uint32_t sl = sm.slot(cur.key);
+            if (sl < sm.n_slots) part[(uint64_t)sl * stride + q] = incl;
+        } else if (incl != identity()) {
+            if constexpr (OP == OP_MAX) atomic_max(out + q, incl);
+            else atomic_sum(out + q, incl);
         }
     }
 };
@@ -377,7 +524,8 @@ struct ForwardProblem {
 // grad_out over the queries after it in its segment, i.e. the queries sharing
 // the tuple and lying strictly above it on the last axis (equal last
 // coordinates put queries first, so they come before the data record and are
-// not counted).  Those partials are summed into grad[data row].
+// not counted).  Those partials go to part[slot * nD + data row], or are
+// summed atomically into grad[data row].
 template <class K, class G>
 struct BackwardProblem {
     using V = G;
@@ -389,6 +537,9 @@ struct BackwardProblem {
     const uint32_t *vals;
     const G *g;
     G *grad;
+    G *part;
+    uint64_t stride;
+    SlotMap sm;
     uint64_t E;
 
     __device__ G identity() const { return G(0); }
@@ -402,8 +553,74 @@ struct BackwardProblem {
         return (cur.payload & kQueryFlag) ? g[cur.payload & ~kQueryFlag] : G(0);
     }
     __device__ void emit(uint64_t, const Raw &cur, G, G excl, G, bool) const {
-        if (!(cur.payload & kQueryFlag) && excl != G(0)) atomic_sum(grad + cur.payload, excl);
+        if (cur.payload & kQueryFlag) return;
+        if (part) {
+            const uint32_t sl = sm.slot(cur.key);
+            if (sl < sm.n_slots) part[(uint64_t)sl * stride + cur.payload] = excl;
+        } else if (excl != G(0)) {
+            atomic_sum(grad + cur.payload, excl);
+        }
     }
 };
+
+// Folds each row's valid slots in slot order: out[o] = F over part[slot][o].
+// Row o is point slot_base + o; its valid slots are the level tuples whose
+// digits of the point's ranks equal `digit` (1 for queries, 0 for data) and
+// lie below the instance's widths.
+struct RegroupArgs {
+    const uint32_t *rank;          // [nax][n] by point slot
+    const uint32_t *inst_of_slot;  // [n] or null
+    const uint8_t *ltab;           // [nax][n_inst]
+    uint32_t n, n_inst;
+    uint32_t slot_base;
+    uint32_t digit;
+    uint32_t radix[3];
+    uint64_t nout;
+};
+
+template <class V, int OP, int NAX>
+__global__ __launch_bounds__(256) void regroup_kernel(RegroupArgs a, const V *__restrict__ part,
+                                                      V *__restrict__ out) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t o = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; o < a.nout; o += stride) {
+        const uint32_t s = a.slot_base + (uint32_t)o;
+        const uint32_t ins = a.inst_of_slot ? a.inst_of_slot[s] : 0u;
+        uint32_t x[3] = {0, 0, 0}, L[3] = {0, 0, 0};
+#pragma unroll
+        for (int ax = 0; ax < NAX; ++ax) {
+            const uint32_t r = a.rank[(uint64_t)ax * a.n + s];
+            L[ax] = a.ltab[(uint64_t)ax * a.n_inst + ins];
+            x[ax] = a.digit ? r : ~r;
+        }
+        // digit j of the L-digit string x, counted from the top, is bit L-1-j
+        auto ok = [&](int ax, uint32_t j) { return j < L[ax] && ((x[ax] >> (L[ax] - 1u - j)) & 1u); };
+        V acc = Monoid<V, OP>::identity();
+        if constexpr (NAX == 0) {
+            acc = part[o];
+        } else if constexpr (NAX == 1) {
+            for (uint32_t j = 0; j < a.radix[0]; ++j)
+                if (ok(0, j)) acc = Monoid<V, OP>::combine(acc, part[(uint64_t)j * a.nout + o]);
+        } else if constexpr (NAX == 2) {
+            for (uint32_t j0 = 0; j0 < a.radix[0]; ++j0) {
+                const bool v0 = ok(0, j0);
+                for (uint32_t j1 = 0; j1 < a.radix[1]; ++j1)
+                    if (v0 && ok(1, j1))
+                        acc = Monoid<V, OP>::combine(acc, part[((uint64_t)j0 * a.radix[1] + j1) * a.nout + o]);
+            }
+        } else {
+            for (uint32_t j0 = 0; j0 < a.radix[0]; ++j0) {
+                const bool v0 = ok(0, j0);
+                for (uint32_t j1 = 0; j1 < a.radix[1]; ++j1) {
+                    const bool v1 = v0 && ok(1, j1);
+                    for (uint32_t j2 = 0; j2 < a.radix[2]; ++j2)
+                        if (v1 && ok(2, j2))
+                            acc = Monoid<V, OP>::combine(
+                                acc, part[(((uint64_t)j0 * a.radix[1] + j1) * a.radix[2] + j2) * a.nout + o]);
+                }
+            }
+        }
+        out[o] = acc;
+    }
+}
 
 }  // namespace domagg

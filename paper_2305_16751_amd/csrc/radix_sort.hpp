@@ -19,23 +19,27 @@ constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kMaxPasses = 8;  // 64-bit keys
 
-// Status word of one (tile, digit): flag in bits 62..63, count below.
-constexpr uint64_t kDigitCountMask = (1ull << 62) - 1;
 
 // ---------------------------------------------------------------------------
 // Fused histogram: add the digits of `key` for passes [0, passes) to the
 // LDS histogram s_hist[passes][256].  All lanes of the wavefront must call
-// it together; lanes with valid = false contribute nothing.  Lanes sharing
-// the first valid lane's digit are added with one atomic (skewed digits, such
-// as the high digits of the tree-node keys, would otherwise serialise).
+// it together; lanes with valid = false contribute nothing.  From pass
+// peel_from on, lanes sharing the first valid lane's digit are added with
+// one atomic (skewed digits, such as the high digits of the tree-node keys,
+// would otherwise serialise on one LDS address).
 template <class K>
-__device__ __forceinline__ void hist_add(uint32_t *s_hist, K key, bool valid, int passes) {
+__device__ __forceinline__ void hist_add(uint32_t *s_hist, K key, bool valid, int passes,
+                                         int peel_from = 0) {
     const uint64_t act = __ballot(valid);
     if (act == 0) return;
     const int leader = __ffsll((unsigned long long)act) - 1;
     const int lane = lane_id();
     for (int p = 0; p < passes; ++p) {
         const uint32_t d = (uint32_t)(key >> (kRadixBits * p)) & (kRadix - 1);
+        if (p < peel_from) {  // digits known to be spread: one LDS atomic per lane
+            if (valid) atomicAdd(&s_hist[p * kRadix + d], 1u);
+            continue;
+        }
         const uint32_t d0 = read_lane_u32(d, leader);
         const uint64_t same = __ballot(valid && d == d0);
         if (lane == leader) atomicAdd(&s_hist[p * kRadix + d0], (uint32_t)__popcll(same));
@@ -66,6 +70,18 @@ __device__ __forceinline__ uint32_t block_excl_sum(uint32_t v, uint32_t *s_tmp, 
     __syncthreads();
     if (total) *total = tot;
     return pre + incl - v;
+}
+
+// First stage of the histogram reduction: block (p, c) sums rows
+// [c*rows, (c+1)*rows) of part[nblocks][passes][256] into part2[c][passes][256].
+__global__ __launch_bounds__(kRadix) void hist_partial_kernel(const uint32_t *__restrict__ part,
+                                                              int nblocks, int passes, int rows,
+                                                              uint32_t *__restrict__ part2) {
+    const int p = blockIdx.x, c = blockIdx.y, d = threadIdx.x;
+    const int b0 = c * rows, b1 = min(nblocks, b0 + rows);
+    uint32_t sum = 0;
+    for (int b = b0; b < b1; ++b) sum += part[((size_t)b * passes + p) * kRadix + d];
+    part2[((size_t)c * passes + p) * kRadix + d] = sum;
 }
 
 // One block per pass: sums the per-block partial histograms and scans them
@@ -103,6 +119,19 @@ __global__ __launch_bounds__(BLOCK) void hist_kernel(const K *__restrict__ keys,
 }
 
 // ---------------------------------------------------------------------------
+// Look-back words of the digit passes: the flag in the top two bits, the
+// count below.  32-bit words when every count fits in 30 bits (n < 2^30),
+// else 64-bit.
+template <class S>
+struct DigitWord {
+    static constexpr int kShift = sizeof(S) * 8 - 2;
+    static constexpr S kMask = (S(1) << kShift) - 1;
+    __device__ static S make(uint32_t flag, uint64_t count) { return (S(flag) << kShift) | S(count); }
+    __device__ static uint32_t flag(S w) { return (uint32_t)(w >> kShift); }
+    __device__ static uint32_t count(S w) { return (uint32_t)(w & kMask); }
+};
+
+// ---------------------------------------------------------------------------
 // One digit pass.  A workgroup takes the next tile from a ticket counter (so
 // every tile it waits on belongs to a workgroup that is already running),
 // ranks its keys by digit within each wavefront (ballot matching, stable in
@@ -110,18 +139,19 @@ __global__ __launch_bounds__(BLOCK) void hist_kernel(const K *__restrict__ keys,
 // for the per-digit offsets (one thread per digit), stages keys and then
 // payloads in LDS in local digit order and writes them out in runs.
 //
-// n < 2^32 - 2*TILE.  status: [tiles][256] words, zero before the launch;
-// ticket: zero before the launch.  digit_base: [256] exclusive bases of the
-// pass's digits over the whole array.  ROLE only names the instantiation
-// (0: per-point coordinate sorts, 1: the sort of the expanded records) so the
-// two show up separately in profiles.
-template <class K, int BLOCK, int ITEMS, int ROLE = 0>
+// n < 2^32 - 2*TILE.  status: [tiles][256] words of type S, zero before the
+// launch; ticket: zero before the launch.  digit_base: [256] exclusive bases
+// of the pass's digits over the whole array.  ROLE only names the
+// instantiation (0: per-point coordinate sorts, 1: the sort of the expanded
+// records) so the two show up separately in profiles.
+template <class K, class S, int BLOCK, int ITEMS, int ROLE = 0>
 __global__ __launch_bounds__(BLOCK) void onesweep_kernel(
     const K *__restrict__ kin, const uint32_t *__restrict__ vin, K *__restrict__ kout,
     uint32_t *__restrict__ vout, uint32_t n, int shift, const uint32_t *__restrict__ digit_base,
-    uint64_t *__restrict__ status, uint32_t *__restrict__ ticket) {
+    S *__restrict__ status, uint32_t *__restrict__ ticket) {
     constexpr int TILE = BLOCK * ITEMS;
     constexpr int WAVES = BLOCK / kWave;
+    using W = DigitWord<S>;
     static_assert(BLOCK >= kRadix, "one thread per digit");
     static_assert(ITEMS <= 32, "");
 
@@ -179,8 +209,8 @@ __global__ __launch_bounds__(BLOCK) void onesweep_kernel(
             s_whist[w][tid] = count;
             count += c;
         }
-        const uint64_t flag = tile == 0 ? kFlagInclusive : kFlagAggregate;
-        store_agent(&status[(uint64_t)tile * kRadix + tid], (flag << 62) | count);
+        store_agent(&status[(uint64_t)tile * kRadix + tid],
+                    W::make(tile == 0 ? kFlagInclusive : kFlagAggregate, count));
     }
     const uint32_t dstart = block_excl_sum<BLOCK>(tid < kRadix ? count : 0u, s_tmp, nullptr);
     if (tid < kRadix) {
@@ -189,15 +219,14 @@ __global__ __launch_bounds__(BLOCK) void onesweep_kernel(
         if (tile > 0) {
             uint32_t t = tile - 1;
             for (;;) {
-                uint64_t w;
-                while (((w = load_agent(&status[(uint64_t)t * kRadix + tid])) >> 62) == 0)
-                    __builtin_amdgcn_s_sleep(1);
-                excl += (uint32_t)(w & kDigitCountMask);
-                if ((w >> 62) == kFlagInclusive) break;
+                S w;
+                while (W::flag(w = load_agent(&status[(uint64_t)t * kRadix + tid])) == 0)
+                    __builtin_amdgcn_s_sleep(2);
+                excl += W::count(w);
+                if (W::flag(w) == kFlagInclusive) break;
                 --t;
             }
-            store_agent(&status[(uint64_t)tile * kRadix + tid],
-                        ((uint64_t)kFlagInclusive << 62) | (uint64_t)(excl + count));
+            store_agent(&status[(uint64_t)tile * kRadix + tid], W::make(kFlagInclusive, excl + count));
         }
         s_goff[tid] = digit_base[tid] + excl - dstart;
     }

@@ -11,6 +11,9 @@
 //   void emit(uint64_t i, const Raw &cur, V v, V excl, V incl, bool last) const;
 // Element 0 always starts a segment; `last` says the element ends its segment.
 //
+// status holds 2 * tiles * (1 or 2) words, zero before the launch (tiles =
+// ceil(n / (BLOCK * ITEMS))).
+//
 // Each workgroup takes a tile from a ticket counter, stages it in LDS with
 // coalesced loads, scans ITEMS consecutive elements per thread, combines
 // threads with a wavefront scan on DPP and the wavefronts through LDS, and
@@ -48,6 +51,8 @@ __global__ __launch_bounds__(BLOCK) void seg_scan_kernel(P p, uint64_t n,
     __syncthreads();
     const uint32_t tile = s_tile;
     const uint64_t base = (uint64_t)tile * TILE;
+    // status: [tiles] inclusive-or-aggregate words, then [tiles] aggregate words
+    uint64_t *const aggs = status + ((n + TILE - 1) / TILE) * ScanStatusWords<V>::kWords;
 
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
@@ -112,32 +117,61 @@ __global__ __launch_bounds__(BLOCK) void seg_scan_kernel(P p, uint64_t n,
     }
     __syncthreads();
 
-    if (tid == 0) {
+    // Wavefront 0 combines the wavefront totals, publishes the tile's status
+    // and looks back.  Every lane computes the same values; lane 0 writes.
+    if (wave == 0) {
         V run = p.identity();
         uint32_t rf = 0;
         for (int w = 0; w < WAVES; ++w) {
-            s_wpre[w] = run;
-            s_wpref[w] = rf;
+            if (lane == 0) {
+                s_wpre[w] = run;
+                s_wpref[w] = rf;
+            }
             run = s_wflag[w] ? s_wval[w] : p.combine(run, s_wval[w]);
             rf |= s_wflag[w];
         }
         // run = the tile's value at its end, counted from its last segment
         // start (rf = 1) or from its beginning (rf = 0)
         const bool first_is_head = (base == 0) || p.head(s_pred, s_raw[0]);
-        publish_status(status, tile, rf ? kFlagInclusive : kFlagAggregate, run);
+        if (lane == 0) {
+            if (!rf) publish_status(aggs, tile, kFlagAggregate, run);
+            publish_status(status, tile, rf ? kFlagInclusive : kFlagAggregate, run);
+        }
         V carry = p.identity();
         if (!first_is_head) {
-            uint32_t t = tile - 1;
+            // Find the nearest earlier tile with an inclusive value, 64 tiles
+            // per round trip (lane l reads tile hi - l), then fold the
+            // aggregates of the tiles after it left to right, 64 per round
+            // trip.  Every inclusive value is therefore the same left fold
+            // from its segment's start whatever the timing, so floating-point
+            // results do not depend on scheduling.
+            int64_t hi = (int64_t)tile - 1, t0 = -1;
+            V incl_v = p.identity();
             for (;;) {
-                V pv;
-                const uint32_t fl = wait_status<V>(status, t, pv);
-                carry = p.combine(pv, carry);
-                if (fl == kFlagInclusive) break;
-                --t;
+                const int64_t t = hi - lane;
+                V pv = p.identity();
+                uint32_t fl = 0;
+                if (t >= 0) fl = wait_status<V>(status, (uint32_t)t, pv);
+                const uint64_t im = __ballot(fl == kFlagInclusive);
+                if (im) {
+                    const int l = __ffsll((unsigned long long)im) - 1;  // nearest
+                    t0 = hi - l;
+                    incl_v = read_lane(pv, l);
+                    break;
+                }
+                hi -= kWave;
             }
-            if (!rf) publish_status(status, tile, kFlagInclusive, p.combine(carry, run));
+            carry = incl_v;
+            for (int64_t w0 = t0 + 1; w0 < (int64_t)tile; w0 += kWave) {
+                const int64_t t = w0 + lane;
+                V av = p.identity();
+                if (t < (int64_t)tile) (void)wait_status<V>(aggs, (uint32_t)t, av);
+                const int cnt = (int)(((int64_t)tile - w0) < kWave ? ((int64_t)tile - w0) : kWave);
+                for (int k = 0; k < cnt; ++k) carry = p.combine(carry, read_lane(av, k));
+            }
+            if (!rf && lane == 0) publish_status(status, tile, kFlagInclusive, p.combine(carry, run));
         }
-        s_carry = carry;
+        if (lane == 0) s_carry = carry;
     }
     __syncthreads();
 

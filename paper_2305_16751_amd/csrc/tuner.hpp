@@ -4,7 +4,7 @@
 // (gfx950, m, record key bits, ceil(log2 E)).
 //
 // Cache file: $DOM_AGG_TUNE_CACHE, else $HOME/.cache/dom_agg_tune.txt; one
-// line per key: "m key_bits log2E record_sort_items scan_items".
+// line per key: "m key_bits log2E record_sort_tile scan_items".
 // DOM_AGG_TUNE=0 disables tuning (defaults are used).
 #pragma once
 
@@ -18,10 +18,12 @@
 namespace domagg {
 
 struct TuneChoice {
-    int record_sort_items = 16;  // onesweep tile = 256 * items
-    int point_sort_items = 16;
-    int scan_items = 16;         // segmented-scan tile = 256 * items (8 forced for 64-bit keys)
+    int record_sort_tile = 4096;  // onesweep tile: 2048 (256 x 8), 4096 (256 x 16) or 8192 (512 x 16)
+    int point_sort_tile = 4096;
+    int scan_items = 16;          // segmented-scan tile = 256 * items (8 forced for 64-bit keys)
 };
+
+inline bool valid_sort_tile(int t) { return t == 2048 || t == 4096 || t == 8192; }
 
 inline TuneChoice default_tune() { return TuneChoice{}; }
 
@@ -54,7 +56,7 @@ class TuneCache {
         if (FILE *f = std::fopen(p.c_str(), "w")) {
             for (auto &kv : map_)
                 std::fprintf(f, "%d %d %d %d %d\n", std::get<0>(kv.first), std::get<1>(kv.first),
-                             std::get<2>(kv.first), kv.second.record_sort_items, kv.second.scan_items);
+                             std::get<2>(kv.first), kv.second.record_sort_tile, kv.second.scan_items);
             std::fclose(f);
         }
     }
@@ -75,9 +77,9 @@ class TuneCache {
         if (!f) return;
         int m, kb, le, rs, sc;
         while (std::fscanf(f, "%d %d %d %d %d", &m, &kb, &le, &rs, &sc) == 5) {
-            if ((rs != 8 && rs != 16) || (sc != 8 && sc != 16)) continue;
+            if (!valid_sort_tile(rs) || (sc != 8 && sc != 16)) continue;
             TuneChoice c;
-            c.record_sort_items = rs;
+            c.record_sort_tile = rs;
             c.scan_items = sc;
             map_[TuneKey{m, kb, le}] = c;
         }

@@ -215,3 +215,37 @@ def test_autograd_function():
     want = oracle.transposed_sum(2, c.D, c.Q, coef.astype(np.float64))
     scale = oracle.transposed_sum(2, c.D, c.Q, np.abs(coef.astype(np.float64)))
     check_fp(w.grad, want, scale, "autograd grad")
+
+
+def test_fp32_results_repeat_bit_for_bit():
+    """Slot regrouping + left-fold look-back: fp32 sums are run-to-run identical."""
+    c = workloads.small_case(12, 2, 60000, 60000, alphabet=None, coord="f32", weight="f32")
+    p = _plan(c)
+    assert p.info()["regroup_slots"] > 0
+    w = to_dev(c.w)
+    g = to_dev(np.random.default_rng(8).standard_normal(c.Q.shape[0]).astype(np.float32))
+    a = p.forward(w, "sum").cpu().numpy()
+    ga = p.backward(g).cpu().numpy()
+    for _ in range(3):
+        assert np.array_equal(p.forward(w, "sum").cpu().numpy(), a)
+        assert np.array_equal(p.backward(g).cpu().numpy(), ga)
+    q = _plan(c)  # a second plan of the same points
+    assert np.array_equal(q.forward(w, "sum").cpu().numpy(), a)
+
+
+def test_atomic_regroup_path_m4():
+    """Wide ranks in m = 4 make the slot table sparse: the plan falls back to
+    atomic F, which must give the same results."""
+    c = workloads.small_case(13, 4, 4000, 4000, alphabet=None, coord="f32", weight="int64")
+    p = _plan(c)
+    assert p.info()["regroup_slots"] == 0, p.info()
+    want = oracle.construction(4, c.D, c.Q, c.w, "sum")
+    check_exact(p.forward(to_dev(c.w), "sum"), want, "atomic sum")
+    check_exact(p.forward(to_dev(c.w), "max"), oracle.construction(4, c.D, c.Q, c.w, "max"), "atomic max")
+    wf = c.w.astype(np.float32)
+    g = np.random.default_rng(9).standard_normal(c.Q.shape[0]).astype(np.float32)
+    gw = p.backward(to_dev(g))
+    check_fp(gw, oracle.transposed_sum(4, c.D, c.Q, g.astype(np.float64)),
+             oracle.transposed_sum(4, c.D, c.Q, np.abs(g.astype(np.float64))), "atomic grad")
+    check_fp(p.forward(to_dev(wf), "sum"), oracle.construction(4, c.D, c.Q, wf.astype(np.float64), "sum"),
+             oracle.construction(4, c.D, c.Q, np.abs(wf.astype(np.float64)), "sum"), "atomic f32 sum")

@@ -42,6 +42,27 @@ def test_int2d_64k_exact():
     np.testing.assert_array_equal(cnt, oracle.fenwick2(c.D, c.Q, None, "count"))
 
 
+def test_f32_2d_2m_counts_and_sums():
+    """Medium size between the small cases and the full workload: long
+    segments (look-back chains over hundreds of tiles), every count exact."""
+    c = workloads.f32_uniform(2, 1 << 21, workloads.BASE_SEED + 21, "f32_2d_2m")
+    print(f"f32_2d_2m |D|={c.D.shape[0]} |Q|={c.Q.shape[0]}", flush=True)
+    p = _plan(c.D, c.Q)
+    cnt = p.forward(None, "count").cpu().numpy()
+    np.testing.assert_array_equal(cnt, oracle.fenwick2(c.D, c.Q, None, "count"))
+    out = p.forward(to_dev(c.w), "sum").cpu().numpy()
+    idx = _sample(c.Q.shape[0], 256, 9)
+    w64 = c.w.astype(np.float64)
+    check_fp(torch.from_numpy(out[idx]), oracle.brute(2, c.D, c.Q[idx], w64, "sum"),
+             oracle.brute(2, c.D, c.Q[idx], np.abs(w64), "sum"), "f32_2d_2m sum")
+    g = np.random.default_rng(10).standard_normal(c.Q.shape[0]).astype(np.float32)
+    gw = p.backward(to_dev(g)).cpu().numpy()
+    di = _sample(c.D.shape[0], 256, 11)
+    g64 = g.astype(np.float64)
+    check_fp(torch.from_numpy(gw[di]), oracle.brute(2, -c.Q.astype(np.float64), -c.D[di].astype(np.float64), g64, "sum"),
+             oracle.brute(2, -c.Q.astype(np.float64), -c.D[di].astype(np.float64), np.abs(g64), "sum"), "grad")
+
+
 def test_f32_2d_16m_sampled():
     c = workloads.f32_2d_16m()
     print(f"f32_2d_16m |D|={c.D.shape[0]} |Q|={c.Q.shape[0]}", flush=True)
