@@ -38,6 +38,20 @@ def key_bytes(info):
     return 4 if info["key_bits"] <= 32 else 8
 
 
+def record_sort_model(info):
+    """Algorithmic bytes of the record sort and its number of digit passes:
+    each pass reads and writes every record of its key-length class once."""
+    rb = key_bytes(info) + 4
+    ncls = info["sort_classes"]
+    total, launches = 0, 0
+    for c, ec in enumerate(info["sort_class_records"]):
+        passes = info["sort_passes"] - ncls + 1 + c
+        if ec:
+            total += passes * 2 * ec * rb
+            launches += passes
+    return total, launches
+
+
 def stage_table(kern, steps, info, n, nax, wbytes=4):
     """Per-kernel average time and, where the kernel has a fixed algorithmic
     byte count, its achieved rate."""
@@ -57,7 +71,8 @@ def stage_table(kern, steps, info, n, nax, wbytes=4):
                "avg_ms_per_launch": round(avg, 5)}
         b = None
         if name.startswith("onesweep_records"):
-            b = 2 * E * (kb + 4)
+            tot, launches = record_sort_model(info)
+            b = tot / max(launches, 1)
         elif name in model:
             b = model[name]
         if b is not None and avg > 0:
@@ -112,13 +127,15 @@ def roofline_entry(kern, info):
         return None
     name, (ms, cnt) = max(rec.items(), key=lambda kv: kv[1][0])
     avg_s = ms / cnt * 1e-3
-    E = info["records"]
-    b = 2 * E * (key_bytes(info) + 4)
+    tot, launches = record_sort_model(info)
+    b = tot / launches
     ach = b / avg_s / 1e9
     return {"bound": "hbm", "kernel": name, "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None,
-            "bytes_per_launch": b, "avg_launch_ms": round(avg_s * 1e3, 5),
-            "bytes_model": "2 * E * (key bytes + 4 payload bytes): read and write of every record per pass"}
+            "bytes_per_launch": round(b), "avg_launch_ms": round(avg_s * 1e3, 5),
+            "bytes_model": "sum over key-length classes of passes_c * 2 * E_c * (key bytes + 4 payload bytes) "
+                           "(every record of a class read and written once per pass of its class), "
+                           "divided by the number of passes"}
 
 
 def cpu_baseline(n_sample=1 << 19):
@@ -253,7 +270,7 @@ def main():
         "config": {"workload": case.name, "m": case.m, "n_data": int(case.D.shape[0]),
                    "n_query": int(case.Q.shape[0]), "op": "sum", "coords": "float32 U[0,1)",
                    "weights": "float32 N(0,1)", "records": info["records"], "key_bits": info["key_bits"],
-                   "sort_passes": info["sort_passes"], "sort_tile": info["sort_tile"],
+                   "sort_passes": info["sort_passes"], "sort_classes": info["sort_classes"], "sort_tile": info["sort_tile"],
                    "scan_tile": info["scan_tile"], "step": "dom_agg_plan + dom_agg_forward"},
         "roofline": roofline_entry(kern, info),
     }

@@ -99,11 +99,14 @@ typedef struct {
     int32_t m;             /* dimension */
     int32_t key_bits;      /* width of the record sort key */
     int32_t L[4];          /* max over instances of ceil(log2 K_i), axes 1..m-1 */
-    int32_t sort_passes;   /* radix passes run by the record sort */
+    int32_t sort_passes;   /* radix passes run by the record sort (its longest class) */
     int32_t digit_bits;    /* radix digit width chosen for the record sort */
     int32_t sort_tile;     /* records per workgroup tile in the record sort */
     int32_t scan_tile;     /* records per workgroup tile in the segmented scans */
     int32_t regroup_slots; /* level-tuple slots of the regrouping; 0 = atomic F instead */
+    int32_t sort_classes;  /* key-length classes the record sort is split into (1 = none) */
+    int64_t sort_class_records[4]; /* records per class (class c is sorted with
+                                      sort_passes - sort_classes + 1 + c passes) */
     size_t workspace_bytes;/* device memory held by the plan */
 } dom_agg_plan_info;
 

@@ -61,12 +61,15 @@ class PlanInfo(ctypes.Structure):
         ("sort_tile", ctypes.c_int32),
         ("scan_tile", ctypes.c_int32),
         ("regroup_slots", ctypes.c_int32),
+        ("sort_classes", ctypes.c_int32),
+        ("sort_class_records", ctypes.c_int64 * 4),
         ("workspace_bytes", ctypes.c_size_t),
     ]
 
     def as_dict(self) -> dict:
-        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "L"}
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("L", "sort_class_records")}
         d["L"] = [self.L[i] for i in range(max(self.m - 1, 0))]
+        d["sort_class_records"] = [self.sort_class_records[i] for i in range(self.sort_classes)]
         return d
 
 

@@ -217,9 +217,26 @@ __device__ __forceinline__ uint32_t wave_sum_scan_incl(uint32_t v) {
     return v;
 }
 
+// Sum of a 64-bit value over each 16-lane row, returned to every lane of
+// the row (every lane must be active).
+__device__ __forceinline__ uint64_t read_lane_u64(uint64_t v, int src);
+__device__ __forceinline__ uint64_t row_sum_u64(uint64_t v) {
+    v += dpp_val<kDppRowShr1, 0xf>(v, (uint64_t)0);
+    v += dpp_val<kDppRowShr2, 0xf>(v, (uint64_t)0);
+    v += dpp_val<kDppRowShr4, 0xf>(v, (uint64_t)0);
+    v += dpp_val<kDppRowShr8, 0xf>(v, (uint64_t)0);
+    return read_lane_u64(v, (lane_id() & ~15) + 15);
+}
+
 // Value of `v` at lane `src` (ds_bpermute; every lane must be active).
 __device__ __forceinline__ uint32_t read_lane_u32(uint32_t v, int src) {
     return (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)v);
+}
+
+__device__ __forceinline__ uint64_t read_lane_u64(uint64_t v, int src) {
+    const uint32_t lo = read_lane_u32((uint32_t)v, src);
+    const uint32_t hi = read_lane_u32((uint32_t)(v >> 32), src);
+    return (uint64_t)lo | ((uint64_t)hi << 32);
 }
 
 template <class V>

@@ -265,13 +265,25 @@ struct dom_agg_plan_s {
     int field_shift[3] = {0, 0, 0};
     int inst_shift = 0;
     int64_t E = 0, E_D = 0;
-    std::vector<int> rec_shifts;  // radix passes the record sort runs
+    std::vector<int> rec_shifts;  // radix passes the record sort runs (without classes)
+    // key-length classes of the record sort (ncls = 1: one sort over all records)
+    int ncls = 1, cls_c0 = 0;
+    int cls_passes[kMaxClasses] = {0, 0, 0, 0};
+    int cls_row0[kMaxClasses] = {0, 0, 0, 0};
+    int cls_rows = 0;
+    uint32_t cls_mask[kMaxClasses] = {0, 0, 0, 0};
+    uint64_t cls_tot[kMaxClasses] = {0, 0, 0, 0};
     TuneChoice tune;
 
     // per-point state, in last-axis order
     DevBuf off, rs, pay, inst_s;
-    // per-point state by slot, kept for the regrouping: ranks, instance, widths
+    // per-point state by internal slot, kept for the regrouping: ranks,
+    // instance, widths
     DevBuf rank, inst_of_slot, ltab;
+    // internal numbering (points in first-axis order; m >= 2): input row of
+    // each data / query position, and a buffer for inputs in that order
+    bool permuted = false;
+    DevBuf dinv, qinv, perm;
     // regrouping: level-tuple slots (slot mode) or atomic F
     uint32_t n_slots = 1;
     bool use_slots = true;
@@ -290,7 +302,7 @@ struct dom_agg_plan_s {
 
     size_t workspace() const {
         return off.bytes + rs.bytes + pay.bytes + inst_s.bytes + rank.bytes + inst_of_slot.bytes + ltab.bytes +
-               part.bytes + rkeys.bytes + rvals.bytes + scan_status.bytes + scan_ticket.bytes + ed_counter.bytes;
+               dinv.bytes + qinv.bytes + perm.bytes + part.bytes + rkeys.bytes + rvals.bytes + scan_status.bytes + scan_ticket.bytes + ed_counter.bytes;
     }
     SlotMap slot_map() const {
         SlotMap sm{};
@@ -326,6 +338,10 @@ struct HostStage {
         return p;
     }
 };
+
+unsigned grid_for(uint64_t n) {
+    return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(ceil_div(n, kBlock), 8192));
+}
 
 template <class T>
 void fill(T *p, uint64_t n, T v, hipStream_t s) {
@@ -475,7 +491,7 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
     }
 
     DevBuf &rank = P->rank;
-    DevBuf kA, kB, vA, vB, kcount, nanflag, part, counts, bases;
+    DevBuf kA, kB, vA, vB, kcount, nanflag, part, counts, bases, ppos;
     kA.alloc((size_t)n * sizeof(KP), s);
     kB.alloc((size_t)n * sizeof(KP), s);
     vA.alloc((size_t)n * 4, s);
@@ -484,6 +500,10 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
         rank.alloc((size_t)nax * n * 4, s);
         kcount.alloc((size_t)nax * ni * 4, s);
         fill(kcount.as<uint32_t>(), (uint64_t)nax * ni, 0u, s);
+        P->permuted = true;
+        ppos.alloc((size_t)n * 4, s);
+        P->dinv.alloc((size_t)P->nD * 4, s);
+        P->qinv.alloc((size_t)P->nQ * 4, s);
     }
     nanflag.alloc(4, s);
     fill(nanflag.as<uint32_t>(), 1, 0u, s);
@@ -503,8 +523,8 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
     for (int axis = 0; axis < m; ++axis) {
         launch("extract_keys", s, [&] {
             extract_keys_kernel<KP, C, kBlock><<<ext_blocks, kBlock, 0, s>>>(
-                qq, dq, m, axis, nQ, n, inst_of_slot.as<uint32_t>(), kA.as<KP>(), vA.as<uint32_t>(),
-                passes, part.as<uint32_t>(), nanflag.as<uint32_t>());
+                qq, dq, m, axis, nQ, n, inst_of_slot.as<uint32_t>(), axis > 0 ? ppos.as<uint32_t>() : nullptr,
+                kA.as<KP>(), vA.as<uint32_t>(), passes, part.as<uint32_t>(), nanflag.as<uint32_t>());
         });
         reduce_hist(part.as<uint32_t>(), (int)ext_blocks, passes, counts.as<uint32_t>(), bases.as<uint32_t>(), s);
         const size_t cb = (size_t)passes * kRadix * 4;
@@ -518,7 +538,23 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
                                         shifts, bases.as<uint32_t>(), P->tune.point_sort_tile, s);
         DevBuf &sk = inB ? kB : kA;
         DevBuf &sv = inB ? vB : vA;
-        if (axis < nax) {
+        if (axis == 0 && nax > 0) {
+            // ranks of the first axis, and the internal numbering of the points
+            RankProblem<KP, true> rp{};
+            rp.keys = sk.as<KP>();
+            rp.slots = sv.as<uint32_t>();
+            rp.rank = rank.as<uint32_t>();
+            rp.kcount = kcount.as<uint32_t>();
+            rp.nQ = nQ;
+            rp.doff = P->batched ? doff_dev.as<int64_t>() : nullptr;
+            rp.qoff = P->batched ? qoff_dev.as<int64_t>() : nullptr;
+            rp.ppos = ppos.as<uint32_t>();
+            rp.dinv = P->dinv.as<uint32_t>();
+            rp.qinv = P->qinv.as<uint32_t>();
+            scan_launch<RankProblem<KP, true>, sizeof(KP) == 4 ? 16 : 8>(
+                "rank_scan", rp, n, scan_status.as<uint64_t>(), scan_status.bytes / 8,
+                scan_ticket.as<uint32_t>(), s);
+        } else if (axis < nax) {
             RankProblem<KP> rp{sk.as<KP>(), sv.as<uint32_t>(), rank.as<uint32_t>() + (size_t)axis * n,
                                kcount.as<uint32_t>() + (size_t)axis * ni};
             scan_launch<RankProblem<KP>, sizeof(KP) == 4 ? 16 : 8>(
@@ -555,6 +591,30 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
     P->key_bits = sum + (P->batched ? P->inst_bits : 0);
     if (P->key_bits > 64) fail(DOM_AGG_ETOOBIG, "record sort key needs %d bits (> 64)", P->key_bits);
     P->key64 = P->key_bits > 32;
+    // Key-length classes (one instance only: the instance bits of a batch sit
+    // above every node id, so nearly all keys would share one class).
+    if (!P->batched && nax >= 1) {
+        const int cmax = (int)ceil_div(P->key_bits, kRadixBits);
+        const int cmin = (int)ceil_div(P->field_shift[0] + 1, kRadixBits);
+        const int nc = std::min(kMaxClasses, cmax - cmin + 1);
+        if (nc >= 2) {
+            P->ncls = nc;
+            P->cls_c0 = cmax - nc + 1;
+            int row = 0;
+            for (int q = 0; q < nc; ++q) {
+                P->cls_passes[q] = P->cls_c0 + q;
+                P->cls_row0[q] = row;
+                row += P->cls_passes[q];
+            }
+            P->cls_rows = row;
+            const int L0 = P->Lmax[0];
+            for (int j = 0; j < L0; ++j) {
+                const int nominal = (int)ceil_div(P->field_shift[0] + j + 1, kRadixBits);
+                const int q = std::max(nominal, P->cls_c0) - P->cls_c0;
+                P->cls_mask[q] |= 1u << (L0 - 1 - j);
+            }
+        }
+    }
     {
         uint64_t S = 1;
         for (int a = 0; a < nax; ++a) S *= (uint64_t)std::max(P->Lmax[a], 1);
@@ -605,10 +665,18 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
 template <class K>
 void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &outK, DevBuf &outV) {
     const uint64_t E = (uint64_t)P->E;
-    DevBuf kA, kB, vA, vB, part, counts, bases;
+    const bool cls = P->ncls > 1;
+    DevBuf kA, kB, vA, vB, part, counts, bases, cstat, ticket;
     kA.alloc(E * sizeof(K), s);
     vA.alloc(E * 4, s);
-    const int passes = std::max(1, (int)ceil_div(P->key_bits, kRadixBits));
+    if (cls) {
+        kB.alloc(E * sizeof(K), s);
+        vB.alloc(E * 4, s);
+    }
+    const int passes = cls ? P->cls_passes[P->ncls - 1] : std::max(1, (int)ceil_div(P->key_bits, kRadixBits));
+    const int rows = cls ? P->cls_rows : passes;
+    if (rows > (sizeof(K) == 4 ? 10 : 26) || passes > kMaxPasses)
+        fail(DOM_AGG_EHIP, "internal: %d histogram rows for %d-byte keys", rows, (int)sizeof(K));
     constexpr int EITEMS = 8;
     constexpr int CHUNK = kBlock * EITEMS;
     constexpr int CHUNK_SHIFT = 11;
@@ -622,9 +690,9 @@ void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &ou
         chunk_start_kernel<<<g, kBlock, 0, s>>>(P->off.as<uint64_t>(), (uint32_t)P->n, CHUNK_SHIFT,
                                                 chunk_k.as<uint32_t>());
     });
-    part.alloc((size_t)grid * passes * kRadix * 4, s);
-    counts.alloc((size_t)passes * kRadix * 4, s);
-    bases.alloc((size_t)passes * kRadix * 4, s);
+    part.alloc((size_t)grid * rows * kRadix * 4, s);
+    counts.alloc((size_t)rows * kRadix * 4, s);
+    bases.alloc((size_t)rows * kRadix * 4, s);
     if (!P->ed_counter.p) P->ed_counter.alloc(8, s);
     fill(P->ed_counter.as<unsigned long long>(), 1, 0ull, s);
 
@@ -643,29 +711,107 @@ void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &ou
     a.passes = passes;
     a.hist_part = part.as<uint32_t>();
     a.data_records = P->ed_counter.as<unsigned long long>();
-    auto emit = [&](auto nax_c) {
+    a.ncls = P->ncls;
+    a.cls_c0 = P->cls_c0;
+    a.hist_rows = rows;
+    for (int q = 0; q < kMaxClasses; ++q) {
+        a.cls_passes[q] = P->cls_passes[q];
+        a.cls_row0[q] = P->cls_row0[q];
+        a.cls_mask[q] = P->cls_mask[q];
+    }
+    auto per_nax = [&](auto &&f) {
+        switch (P->nax) {
+            case 0: f(std::integral_constant<int, 0>{}); break;
+            case 1: f(std::integral_constant<int, 1>{}); break;
+            case 2: f(std::integral_constant<int, 2>{}); break;
+            default: f(std::integral_constant<int, 3>{}); break;
+        }
+    };
+    if (cls) {
+        if (probe) {
+            DevBuf tot;
+            tot.alloc(kMaxClasses * 8, s);
+            fill(tot.as<unsigned long long>(), kMaxClasses, 0ull, s);
+            per_nax([&](auto nax_c) {
+                constexpr int NAX = decltype(nax_c)::value;
+                launch("class_count", s, [&] {
+                    class_count_kernel<NAX><<<grid_for(P->n), kBlock, 0, s>>>(a, tot.as<unsigned long long>());
+                });
+            });
+            uint64_t *h = static_cast<uint64_t *>(hs->get(kMaxClasses * 8));
+            HIPCHK(hipMemcpyAsync(h, tot.p, kMaxClasses * 8, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            uint64_t sum = 0;
+            for (int q = 0; q < kMaxClasses; ++q) {
+                P->cls_tot[q] = h[q];
+                sum += h[q];
+            }
+            if (sum != E) fail(DOM_AGG_EHIP, "internal: class totals %llu != E %llu", (unsigned long long)sum,
+                               (unsigned long long)E);
+        }
+        uint64_t base = 0;
+        for (int q = 0; q < kMaxClasses; ++q) {
+            a.cls_base[q] = base;
+            base += P->cls_tot[q];
+        }
+        cstat.alloc(nchunks * kMaxClasses * 8, s);
+    }
+    ticket.alloc(16, s);
+    clear_lookback(cstat.as<uint64_t>(), cls ? nchunks * kMaxClasses : 0, ticket.as<uint32_t>(), s);
+    fill(ticket.as<uint32_t>() + 1, 1, 0u, s);
+    a.cls_status = cstat.as<unsigned long long>();
+    a.ticket = ticket.as<uint32_t>();
+    a.error = ticket.as<uint32_t>() + 1;
+    per_nax([&](auto nax_c) {
         constexpr int NAX = decltype(nax_c)::value;
         launch("flatmap_emit", s, [&] {
-            emit_kernel<K, NAX, kBlock, EITEMS><<<grid, kBlock, 0, s>>>(a, kA.as<K>(), vA.as<uint32_t>());
+            if (cls)
+                emit_kernel<K, NAX, kBlock, EITEMS, true><<<grid, kBlock, 0, s>>>(a, kA.as<K>(), vA.as<uint32_t>(),
+                                                                                  kB.as<K>(), vB.as<uint32_t>());
+            else
+                emit_kernel<K, NAX, kBlock, EITEMS, false><<<grid, kBlock, 0, s>>>(a, kA.as<K>(), vA.as<uint32_t>(),
+                                                                                   nullptr, nullptr);
         });
-    };
-    switch (P->nax) {
-        case 0: emit(std::integral_constant<int, 0>{}); break;
-        case 1: emit(std::integral_constant<int, 1>{}); break;
-        case 2: emit(std::integral_constant<int, 2>{}); break;
-        default: emit(std::integral_constant<int, 3>{}); break;
-    }
-    reduce_hist(part.as<uint32_t>(), (int)grid, passes, counts.as<uint32_t>(), bases.as<uint32_t>(), s);
+    });
+    reduce_hist(part.as<uint32_t>(), (int)grid, rows, counts.as<uint32_t>(), bases.as<uint32_t>(), s);
     if (probe) {
-        const size_t cb = (size_t)passes * kRadix * 4;
-        uint32_t *h = static_cast<uint32_t *>(hs->get(cb + 8));
+        const size_t cb = (size_t)rows * kRadix * 4;
+        uint32_t *h = static_cast<uint32_t *>(hs->get(cb + 12));
         HIPCHK(hipMemcpyAsync(h, counts.p, cb, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpyAsync(h + passes * kRadix, P->ed_counter.p, 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(h + rows * kRadix, P->ed_counter.p, 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(h + rows * kRadix + 2, ticket.as<uint32_t>() + 1, 4, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        P->rec_shifts = P->key_bits ? live_shifts(h, passes, E) : std::vector<int>{};
+        if (h[rows * kRadix + 2]) fail(DOM_AGG_EHIP, "internal: flat-map records disagree with their class counts");
+        if (cls) {
+            P->rec_shifts.clear();
+            for (int p = 0; p < passes; ++p) P->rec_shifts.push_back(p * kRadixBits);
+        } else {
+            P->rec_shifts = P->key_bits ? live_shifts(h, passes, E) : std::vector<int>{};
+        }
         uint64_t ed;
-        std::memcpy(&ed, h + passes * kRadix, 8);
+        std::memcpy(&ed, h + rows * kRadix, 8);
         P->E_D = (int64_t)ed;
+    }
+    if (cls) {
+        // every region ends in B (see EmitArgs)
+        for (int q = 0; q < P->ncls; ++q) {
+            const uint64_t nq = P->cls_tot[q];
+            if (nq == 0) continue;
+            const int np = P->cls_passes[q];
+            std::vector<int> shifts;
+            for (int p = 0; p < np; ++p) shifts.push_back(p * kRadixBits);
+            const uint64_t b = a.cls_base[q];
+            const uint32_t *cb = bases.as<uint32_t>() + (size_t)P->cls_row0[q] * kRadix;
+            if (np & 1)
+                radix_sort<K, 1>(kA.as<K>() + b, vA.as<uint32_t>() + b, kB.as<K>() + b, vB.as<uint32_t>() + b, nq,
+                                 shifts, cb, P->tune.record_sort_tile, s);
+            else
+                radix_sort<K, 1>(kB.as<K>() + b, vB.as<uint32_t>() + b, kA.as<K>() + b, vA.as<uint32_t>() + b, nq,
+                                 shifts, cb, P->tune.record_sort_tile, s);
+        }
+        outK = std::move(kB);
+        outV = std::move(vB);
+        return;
     }
     bool inB = false;
     if (!P->rec_shifts.empty()) {
@@ -695,6 +841,7 @@ void records_for_call(Plan *P, hipStream_t s, DevBuf &k, DevBuf &v, const void *
 
 RegroupArgs regroup_args(const Plan *P, bool queries) {
     RegroupArgs r{};
+    r.inv = P->permuted ? (queries ? P->qinv.as<uint32_t>() : P->dinv.as<uint32_t>()) : nullptr;
     r.rank = P->rank.as<uint32_t>();
     r.inst_of_slot = P->inst_of_slot.as<uint32_t>();
     r.ltab = P->ltab.as<uint8_t>();
@@ -734,11 +881,27 @@ V host_identity() {
     }
 }
 
-// The slot table of the regrouping, sized before any graph capture.
+// The plan's per-call buffers, sized before any graph capture: inputs in
+// internal order, and the slot table of the regrouping (or, in atomic mode,
+// the atomic target in internal order).
 void ensure_part(Plan *P, size_t vbytes, hipStream_t s) {
-    if (!P->use_slots || P->nax == 0) return;
-    const size_t need = (size_t)P->n_slots * (size_t)std::max(P->nQ, P->nD) * vbytes;
+    const size_t rows = (size_t)std::max(P->nQ, P->nD);
+    if (P->permuted && P->perm.bytes < rows * 8) P->perm.alloc(rows * 8, s);
+    if (P->nax == 0) return;
+    const size_t need = P->use_slots ? (size_t)P->n_slots * rows * vbytes : rows * vbytes;
     if (P->part.bytes < need) P->part.alloc(need, s);
+}
+
+template <class T>
+void gather(const T *src, const uint32_t *idx, T *dst, uint64_t n, hipStream_t s) {
+    if (n == 0) return;
+    launch("permute_in", s, [&] { gather_kernel<T><<<grid_for(n), kBlock, 0, s>>>(src, idx, dst, n); });
+}
+
+template <class T>
+void scatter(const T *src, const uint32_t *idx, T *dst, uint64_t n, hipStream_t s) {
+    if (n == 0) return;
+    launch("permute_out", s, [&] { scatter_kernel<T><<<grid_for(n), kBlock, 0, s>>>(src, idx, dst, n); });
 }
 
 template <class K, class W, class V, int OP>
@@ -747,15 +910,22 @@ void forward_typed(Plan *P, const void *kp, const uint32_t *vp, const void *w, v
     fp.keys = static_cast<const K *>(kp);
     fp.vals = vp;
     fp.w = static_cast<const W *>(w);
-    fp.out = static_cast<V *>(out);
+    if constexpr (OP != OP_COUNT) {
+        if (P->permuted && P->nD > 0) {
+            gather(static_cast<const W *>(w), P->dinv.as<uint32_t>(), P->perm.as<W>(), (uint64_t)P->nD, s);
+            fp.w = P->perm.as<W>();
+        }
+    }
+    V *const res = static_cast<V *>(out);
     fp.sm = P->slot_map();
     fp.stride = (uint64_t)P->nQ;
     if (P->use_slots) {
         // m = 1: every query has exactly one record, so it is stored in place
-        fp.part = P->nax == 0 ? static_cast<V *>(out) : P->part.as<V>();
+        fp.part = P->nax == 0 ? res : P->part.as<V>();
     } else {
         fp.part = nullptr;
-        fill(static_cast<V *>(out), (uint64_t)P->nQ, host_identity<V, OP>(), s);
+        fp.out = P->permuted ? P->part.as<V>() : res;
+        fill(fp.out, (uint64_t)P->nQ, host_identity<V, OP>(), s);
     }
     if (P->tune.scan_items == 8 || sizeof(K) == 8)
         scan_launch<ForwardProblem<K, W, V, OP>, 8>("forward_scan", fp, (uint64_t)P->E,
@@ -765,7 +935,8 @@ void forward_typed(Plan *P, const void *kp, const uint32_t *vp, const void *w, v
         scan_launch<ForwardProblem<K, W, V, OP>, 16>("forward_scan", fp, (uint64_t)P->E,
                                                      P->scan_status.as<uint64_t>(), P->scan_words,
                                                      P->scan_ticket.as<uint32_t>(), s);
-    if (P->use_slots && P->nax > 0) regroup<V, OP>(P, true, P->part.as<V>(), static_cast<V *>(out), s);
+    if (P->use_slots && P->nax > 0) regroup<V, OP>(P, true, P->part.as<V>(), res, s);
+    else if (!P->use_slots && P->permuted) scatter(P->part.as<V>(), P->qinv.as<uint32_t>(), res, (uint64_t)P->nQ, s);
 }
 
 template <class K>
@@ -795,15 +966,20 @@ void backward_typed(Plan *P, const void *kp, const uint32_t *vp, const void *g, 
     bp.keys = static_cast<const K *>(kp);
     bp.vals = vp;
     bp.g = static_cast<const G *>(g);
-    bp.grad = static_cast<G *>(grad);
+    if (P->permuted && P->nQ > 0) {
+        gather(static_cast<const G *>(g), P->qinv.as<uint32_t>(), P->perm.as<G>(), (uint64_t)P->nQ, s);
+        bp.g = P->perm.as<G>();
+    }
+    G *const res = static_cast<G *>(grad);
     bp.sm = P->slot_map();
     bp.stride = (uint64_t)P->nD;
     bp.E = (uint64_t)P->E;
     if (P->use_slots) {
-        bp.part = P->nax == 0 ? static_cast<G *>(grad) : P->part.as<G>();
+        bp.part = P->nax == 0 ? res : P->part.as<G>();
     } else {
         bp.part = nullptr;
-        fill(static_cast<G *>(grad), (uint64_t)P->nD, G(0), s);
+        bp.grad = P->permuted ? P->part.as<G>() : res;
+        fill(bp.grad, (uint64_t)P->nD, G(0), s);
     }
     if (P->tune.scan_items == 8 || sizeof(K) == 8)
         scan_launch<BackwardProblem<K, G>, 8>("backward_scan", bp, (uint64_t)P->E, P->scan_status.as<uint64_t>(),
@@ -811,7 +987,8 @@ void backward_typed(Plan *P, const void *kp, const uint32_t *vp, const void *g, 
     else
         scan_launch<BackwardProblem<K, G>, 16>("backward_scan", bp, (uint64_t)P->E, P->scan_status.as<uint64_t>(),
                                                P->scan_words, P->scan_ticket.as<uint32_t>(), s);
-    if (P->use_slots && P->nax > 0) regroup<G, OP_SUM>(P, false, P->part.as<G>(), static_cast<G *>(grad), s);
+    if (P->use_slots && P->nax > 0) regroup<G, OP_SUM>(P, false, P->part.as<G>(), res, s);
+    else if (!P->use_slots && P->permuted) scatter(P->part.as<G>(), P->dinv.as<uint32_t>(), res, (uint64_t)P->nD, s);
 }
 
 // Runs `body` directly, or through the plan's HIP graph in DOM_AGG_GRAPH mode.
@@ -873,16 +1050,25 @@ float time_ms(hipStream_t s, const std::function<void()> &f) {
     return ms;
 }
 
+TuneKey tune_key(const Plan *P) { return TuneKey{P->m, P->key_bits, bits_for((uint64_t)P->E)}; }
+
+// Applies a cached choice; called before the records are built, so that the
+// plan's own record sort runs with it.
+bool tune_lookup(Plan *P) {
+    TuneCache &tc = TuneCache::get();
+    if (!tc.enabled() || P->E <= 0) return false;
+    TuneChoice c;
+    if (!tc.lookup(tune_key(P), &c)) return false;
+    P->tune.record_sort_tile = c.record_sort_tile;
+    P->tune.scan_items = c.scan_items;
+    return true;
+}
+
+// Times the candidates (no cached choice yet) and stores the fastest.
 void tune_plan(Plan *P, hipStream_t s) {
     TuneCache &tc = TuneCache::get();
     if (!tc.enabled() || P->E <= 0) return;
-    const TuneKey key{P->m, P->key_bits, bits_for((uint64_t)P->E)};
-    TuneChoice c;
-    if (tc.lookup(key, &c)) {
-        P->tune.record_sort_tile = c.record_sort_tile;
-        P->tune.scan_items = c.scan_items;
-        return;
-    }
+    const TuneKey key = tune_key(P);
     // the per-point state is still present here (plan construction)
     float best = 1e30f;
     int best_tile = P->tune.record_sort_tile;
@@ -1021,12 +1207,13 @@ dom_agg_status dom_agg_plan(dom_agg_plan_t *plan, int m, dom_agg_dtype coord_dty
             P->scan_status.alloc(P->scan_words * 8, s);
             P->scan_ticket.alloc(16, s);
             if (P->E > 0) {
+                const bool tuned = !(flags & DOM_AGG_NO_TUNE) && tune_lookup(P.get());
                 DevBuf k, v;
                 if (P->key64) build_records<uint64_t>(P.get(), s, &hs, true, k, v);
                 else build_records<uint32_t>(P.get(), s, &hs, true, k, v);
                 P->rkeys = std::move(k);
                 P->rvals = std::move(v);
-                if (!(flags & DOM_AGG_NO_TUNE)) tune_plan(P.get(), s);
+                if (!(flags & DOM_AGG_NO_TUNE) && !tuned) tune_plan(P.get(), s);
                 if (flags & DOM_AGG_RECOMPUTE) {
                     P->rkeys.reset();
                     P->rvals.reset();
@@ -1125,6 +1312,11 @@ dom_agg_status dom_agg_plan_get_info(dom_agg_plan_t plan, dom_agg_plan_info *inf
         info->sort_tile = plan->tune.record_sort_tile;
         info->scan_tile = kBlock * ((plan->tune.scan_items == 8 || plan->key64) ? 8 : 16);
         info->regroup_slots = plan->use_slots ? (int32_t)plan->n_slots : 0;
+        info->sort_classes = plan->ncls;
+        if (plan->ncls > 1)
+            for (int q = 0; q < plan->ncls; ++q) info->sort_class_records[q] = (int64_t)plan->cls_tot[q];
+        else
+            info->sort_class_records[0] = plan->E;
         info->workspace_bytes = plan->workspace();
     });
 }

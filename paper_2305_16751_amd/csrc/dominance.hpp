@@ -13,6 +13,8 @@
 //     gradient.
 #pragma once
 
+#include <type_traits>
+
 #include "device_common.hpp"
 #include "radix_sort.hpp"
 
@@ -34,12 +36,13 @@ __device__ __forceinline__ bool is_nan(float x) { return x != x; }
 __device__ __forceinline__ bool is_nan(int32_t) { return false; }
 
 // keys[s] = (instance << 32 | ordered coordinate) or the ordered coordinate;
-// vals[s] = s.  Fused histogram of `passes` digits; NaN raises *nan_flag.
+// vals[s] = the point's internal slot, ppos[s] (or s while ppos is not yet
+// known).  Fused histogram of `passes` digits; NaN raises *nan_flag.
 template <class K, class C, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void extract_keys_kernel(
     const C *__restrict__ q, const C *__restrict__ d, int m, int axis, uint32_t nQ, uint32_t n,
-    const uint32_t *__restrict__ inst_of_slot, K *__restrict__ keys, uint32_t *__restrict__ vals,
-    int passes, uint32_t *__restrict__ hist_part, uint32_t *__restrict__ nan_flag) {
+    const uint32_t *__restrict__ inst_of_slot, const uint32_t *__restrict__ ppos, K *__restrict__ keys,
+    uint32_t *__restrict__ vals, int passes, uint32_t *__restrict__ hist_part, uint32_t *__restrict__ nan_flag) {
     __shared__ uint32_t s_hist[kMaxPasses * kRadix];
     for (int i = threadIdx.x; i < passes * kRadix; i += BLOCK) s_hist[i] = 0;
     __syncthreads();
@@ -57,7 +60,7 @@ __global__ __launch_bounds__(BLOCK) void extract_keys_kernel(
                 if (inst_of_slot) key |= (K)inst_of_slot[s] << 32;
             }
             keys[s] = key;
-            vals[s] = (uint32_t)s;
+            vals[s] = ppos ? ppos[s] : (uint32_t)s;
         }
         hist_add(s_hist, key, valid, passes);
     }
@@ -104,10 +107,22 @@ __global__ void clear_lookback_kernel(uint64_t *__restrict__ status, uint64_t wo
 // element compares with -inf); its inclusive sum restarted at every instance
 // is the 1-based rank.  The last element of each instance holds K, the number
 // of distinct coordinates.  rank[slot] receives the 0-based rank.
+//
+// Internal numbering (POS, first expanded axis only).  Every later stage
+// numbers points by their order on this axis instead of by input row: data
+// point d becomes dpos = the number of data points before it in the sorted
+// list, query q becomes qpos likewise, and the internal slot is qpos or
+// nQ + dpos (queries first, as for input slots).  Instance ranges are kept
+// (positions of instance k lie in [off[k], off[k+1])).  This is a relabelling
+// only; the method's lists are unchanged.  What it buys: the records of a
+// tree node on this axis come from a contiguous rank range, so their data
+// and query labels fall in a narrow window, and the scans' weight gathers and
+// partial stores stay in cache instead of striding over all of HBM.  The
+// count of data points rides in the high half of the scan value.
 
-template <class K>
+template <class K, bool POS = false>
 struct RankProblem {
-    using V = uint32_t;
+    using V = typename std::conditional<POS, uint64_t, uint32_t>::type;
     struct Raw {
         K key;
         uint32_t slot;
@@ -116,23 +131,68 @@ struct RankProblem {
     const uint32_t *slots;
     uint32_t *rank;
     uint32_t *kcount;  // [n_inst]
+    // POS only
+    uint32_t nQ;
+    const int64_t *doff, *qoff;  // instance offsets of data and queries, or null (one instance)
+    uint32_t *ppos;              // [n] by input slot: the internal slot
+    uint32_t *dinv, *qinv;       // [nD], [nQ]: input row of each position
 
     __device__ static uint32_t inst(const Raw &r) {
         if constexpr (sizeof(K) == 8) return (uint32_t)(r.key >> 32);
         else return 0u;
     }
-    __device__ V identity() const { return 0u; }
+    __device__ V identity() const { return V(0); }
     __device__ V combine(V a, V b) const { return a + b; }
     __device__ Raw load(uint64_t i) const { return Raw{keys[i], slots[i]}; }
     __device__ bool head(const Raw &prev, const Raw &cur) const { return inst(prev) != inst(cur); }
     __device__ V value(const Raw &prev, bool has_prev, const Raw &cur, uint64_t) const {
-        return (!has_prev || prev.key != cur.key) ? 1u : 0u;
+        const V distinct = (!has_prev || prev.key != cur.key) ? V(1) : V(0);
+        if constexpr (POS) return distinct | ((uint64_t)(cur.slot >= nQ) << 32);
+        else return distinct;
     }
-    __device__ void emit(uint64_t, const Raw &cur, V, V, V incl, bool last) const {
-        rank[cur.slot] = incl - 1u;
-        if (last) kcount[inst(cur)] = incl;
+    __device__ void emit(uint64_t i, const Raw &cur, V, V, V incl, bool last) const {
+        const uint32_t r = (uint32_t)incl - 1u;
+        const uint32_t ins = inst(cur);
+        if constexpr (POS) {
+            // data points up to and including element i, in this instance
+            const uint64_t cd = incl >> 32;
+            const uint64_t dbase = doff ? (uint64_t)doff[ins] : 0ull;
+            uint32_t sp;
+            if (cur.slot >= nQ) {
+                const uint32_t p = (uint32_t)(dbase + cd - 1u);
+                dinv[p] = cur.slot - nQ;
+                sp = nQ + p;
+            } else {
+                // element i is the (i - dbase - qbase)-th of its instance,
+                // cd of those before it are data
+                const uint32_t p = (uint32_t)(i - dbase - cd);
+                qinv[p] = cur.slot;
+                sp = p;
+            }
+            ppos[cur.slot] = sp;
+            rank[sp] = r;
+        } else {
+            rank[cur.slot] = r;
+        }
+        if (last) kcount[ins] = (uint32_t)incl;
     }
 };
+
+// dst[p] = src[idx[p]]: inputs into internal order.
+template <class T>
+__global__ void gather_kernel(const T *__restrict__ src, const uint32_t *__restrict__ idx, T *__restrict__ dst,
+                              uint64_t n) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) dst[p] = src[idx[p]];
+}
+
+// dst[idx[p]] = src[p]: results back into input order.
+template <class T>
+__global__ void scatter_kernel(const T *__restrict__ src, const uint32_t *__restrict__ idx, T *__restrict__ dst,
+                               uint64_t n) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) dst[idx[p]] = src[p];
+}
 
 // ---------------------------------------------------------------------------
 // Flat-map sizes.  Over the points in last-axis order (slot list `slots`,
@@ -200,6 +260,17 @@ struct CountProblem {
 // last-axis order and the record sort is stable, which yields the Sec. 5
 // order inside every segment.
 
+// Key-length classes.  The sort only has to bring equal keys together (any
+// order of the segments will do) and keep the last-axis order inside them.
+// A node id at level j has j + 1 significant bits, so shallow levels need
+// fewer 8-bit digit passes.  With classes, the flat map writes each record
+// into the region of its class -- the number of digits covering its key,
+// clamped below so that there are at most kMaxClasses -- keeping last-axis
+// order inside the region, and each region is sorted with its own number of
+// passes.  Class c of cls_passes[c] passes is written to buffer A when that
+// number is odd and to B when it is even, so that every region ends in B.
+constexpr int kMaxClasses = 4;
+
 struct EmitArgs {
     const uint64_t *off;      // [n + 1]
     const uint32_t *rs;       // [NAX][n]
@@ -211,10 +282,35 @@ struct EmitArgs {
     uint64_t E;
     int field_shift[3];
     int inst_shift;
-    int passes;
+    int passes;               // digit passes (the largest class's, with classes)
     uint32_t *hist_part;
     unsigned long long *data_records;
+    // classes (ncls = 1: records are written in last-axis order to buffer A)
+    int ncls;
+    int cls_c0;                          // digit count of class 0
+    int cls_passes[kMaxClasses];
+    int cls_row0[kMaxClasses];           // first histogram row of each class
+    int hist_rows;                       // sum of cls_passes
+    uint64_t cls_base[kMaxClasses];      // region starts
+    uint32_t cls_mask[kMaxClasses];      // first-axis levels of each class (bit L-1-j for level j)
+    unsigned long long *cls_status;      // [chunks][kMaxClasses] look-back words
+    uint32_t *ticket;
+    uint32_t *error;                     // set when a chunk's records disagree with its class counts
 };
+
+// Sum of the 16-bit fields of `packed` below field q (q <= 4).
+__device__ __forceinline__ uint32_t packed_prefix(uint64_t packed, int q) {
+    const uint64_t x = packed & (q >= 4 ? ~0ull : ((1ull << (16 * q)) - 1ull));
+    return (uint32_t)(x & 0xffffu) + (uint32_t)((x >> 16) & 0xffffu) + (uint32_t)((x >> 32) & 0xffffu) +
+           (uint32_t)(x >> 48);
+}
+
+template <class K>
+__device__ __forceinline__ int key_class(K key, int c0) {
+    const int bits = (int)(sizeof(K) * 8) - (sizeof(K) == 8 ? __clzll((long long)key) : __clz((int)key));
+    const int nominal = (bits + kRadixBits - 1) / kRadixBits;
+    return (nominal > c0 ? nominal : c0) - c0;
+}
 
 // chunk_k[c] = the point k with off[k] <= c * chunk < off[k+1].
 __global__ void chunk_start_kernel(const uint64_t *__restrict__ off, uint32_t n, int chunk_shift,
@@ -315,6 +411,63 @@ struct PointWalk {
     }
 };
 
+
+// Records of each class among the records [ta, tb) of one point, packed in
+// 16-bit fields.  The walk visits the first axis slowest and its levels in
+// increasing order (the highest remaining digit of the rank string first),
+// and classes are increasing ranges of first-axis levels, so the records of
+// class q are indices [R s_q, R (s_q + n_q)): n_q levels of the point fall
+// in class q, s_q in the classes before it, R = records per first-axis level.
+template <int NAX>
+__device__ __forceinline__ uint64_t point_class_counts(const EmitArgs &a, uint32_t pay, const uint32_t *ranks,
+                                                       uint32_t ta, uint32_t tb) {
+    const bool isq = (pay & kQueryFlag) != 0u;
+    uint32_t full0 = 0, R = 1;
+#pragma unroll
+    for (int ax = 0; ax < NAX; ++ax) {
+        const uint32_t L = a.ltab[ax];
+        const uint32_t mask = L >= 32u ? 0xffffffffu : ((1u << L) - 1u);
+        const uint32_t full = isq ? (ranks[ax] & mask) : (~ranks[ax] & mask);
+        if (ax == 0) full0 = full;
+        else R *= (uint32_t)__popc(full);
+    }
+    uint64_t packed = 0;
+    uint32_t s = 0;
+#pragma unroll
+    for (int q = 0; q < kMaxClasses; ++q) {
+        const uint32_t nq = (uint32_t)__popc(full0 & a.cls_mask[q]);
+        const uint32_t lo = R * s, hi = R * (s + nq);
+        const uint32_t x0 = ta < lo ? lo : (ta > hi ? hi : ta);
+        const uint32_t x1 = tb < lo ? lo : (tb > hi ? hi : tb);
+        packed |= (uint64_t)(x1 - x0) << (16 * q);
+        s += nq;
+    }
+    return packed;
+}
+
+// Records per class over all points (one instance).
+template <int NAX>
+__global__ __launch_bounds__(256) void class_count_kernel(EmitArgs a, unsigned long long *__restrict__ cls_tot) {
+    __shared__ unsigned long long s_tot[kMaxClasses];
+    if (threadIdx.x < kMaxClasses) s_tot[threadIdx.x] = 0;
+    __syncthreads();
+    unsigned long long acc[kMaxClasses] = {0, 0, 0, 0};
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.n; k += stride) {
+        uint32_t rk[NAX > 0 ? NAX : 1];
+#pragma unroll
+        for (int ax = 0; ax < NAX; ++ax) rk[ax] = a.rs[(uint64_t)ax * a.n + k];
+        const uint64_t pc = point_class_counts<NAX>(a, a.pay[k], rk, 0u, 0xffffffffu);
+#pragma unroll
+        for (int q = 0; q < kMaxClasses; ++q) acc[q] += (pc >> (16 * q)) & 0xffffu;
+    }
+#pragma unroll
+    for (int q = 0; q < kMaxClasses; ++q)
+        if (acc[q]) atomicAdd(&s_tot[q], acc[q]);
+    __syncthreads();
+    if (threadIdx.x < kMaxClasses && s_tot[threadIdx.x]) atomicAdd(cls_tot + threadIdx.x, s_tot[threadIdx.x]);
+}
+
 // The flat map (Sec. 4 with Sec. 5).  Record o belongs to the point k with
 // off[k] <= o < off[k+1]; its index t = o - off[k] enumerates the product of
 // the point's per-axis prefix sets, last expanded axis fastest.  On axis a
@@ -325,30 +478,100 @@ struct PointWalk {
 // last-axis order and the record sort is stable, which yields the Sec. 5
 // order inside every segment.
 //
-// A block takes a chunk of CHUNK consecutive records; the state of the
-// chunk's points is loaded into LDS with coalesced reads; each thread then
-// produces ITEMS consecutive records (one search for its first, then a walk),
-// stages keys and payloads in LDS, and the block writes them out coalesced.
-// The radix histogram of every pass is accumulated on the way.
-template <class K, int NAX, int BLOCK, int ITEMS>
-__global__ __launch_bounds__(BLOCK) void emit_kernel(EmitArgs a, K *__restrict__ keys_out,
-                                                     uint32_t *__restrict__ vals_out) {
+// A block takes a chunk of CHUNK consecutive records (from a ticket, so that
+// every chunk it waits on is held by a running block) and loads the state of
+// the chunk's points into LDS with coalesced reads.  Each thread produces
+// ITEMS consecutive records (one search for its first, then a walk) and
+// stages them in LDS.  Without classes the block then writes them out in
+// place.  With classes, each thread first counts its records per class from
+// its points (closed form, see point_class_counts); one block scan of those
+// counts gives every record its slot in a class-split staging and the
+// chunk's counts, which are published before the walk.  After the walk,
+// wavefront 0 looks back over earlier chunks for each class's offset and the
+// block writes each class's run into its region.  The digit histograms of
+// every pass (of every class) are accumulated on the way.
+
+// Adds the digits of `key` for passes [0, np) to histogram rows row0 + p;
+// lanes sharing the first active lane's row and digit are added with one
+// atomic.  All lanes of the wavefront call it, for max_np passes.
+template <class K>
+__device__ __forceinline__ void hist_add_rows(uint32_t *s_hist, K key, bool valid, int row0, int np, int max_np) {
+    const int lane = lane_id();
+    for (int p = 0; p < max_np; ++p) {
+        const bool v = valid && p < np;
+        const uint64_t act = __ballot(v);
+        if (act == 0) continue;
+        const int leader = __ffsll((unsigned long long)act) - 1;
+        const uint32_t idx = (uint32_t)(row0 + p) * kRadix + ((uint32_t)(key >> (kRadixBits * p)) & (kRadix - 1));
+        const uint32_t i0 = read_lane_u32(idx, leader);
+        const uint64_t same = __ballot(v && idx == i0);
+        if (lane == leader) atomicAdd(&s_hist[i0], (uint32_t)__popcll(same));
+        if (v && idx != i0) atomicAdd(&s_hist[idx], 1u);
+    }
+}
+
+// Exclusive sum of packed 16-bit counters over a block (each field's block
+// total must stay below 2^16); *total gets the packed block sums.
+template <int BLOCK>
+__device__ __forceinline__ uint64_t block_excl_sum_packed(uint64_t v, uint64_t *s_tmp, uint64_t *total) {
+    const int lane = lane_id(), wave = threadIdx.x / kWave;
+    uint64_t incl = v;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint64_t o = read_lane_u64(incl, lane >= d ? lane - d : 0);
+        if (lane >= d) incl += o;
+    }
+    if (lane == kWave - 1) s_tmp[wave] = incl;
+    __syncthreads();
+    uint64_t pre = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < BLOCK / kWave; ++w) {
+        const uint64_t t = s_tmp[w];
+        pre += (w < wave) ? t : 0ull;
+        tot += t;
+    }
+    __syncthreads();
+    *total = tot;
+    return pre + incl - v;
+}
+
+template <class K, int NAX, int BLOCK, int ITEMS, bool CLS>
+__global__ __launch_bounds__(BLOCK) void emit_kernel(EmitArgs a, K *__restrict__ keys_a, uint32_t *__restrict__ vals_a,
+                                                     K *__restrict__ keys_b, uint32_t *__restrict__ vals_b) {
     constexpr int CHUNK = BLOCK * ITEMS;
+    // histogram rows: passes of every class (up to 1+2+3+4 for 32-bit keys)
+    constexpr int kRows = CLS ? (sizeof(K) == 4 ? 10 : 26) : kMaxPasses;
     using PC = PointCache<NAX>;
+    using DW = DigitWord<unsigned long long>;
     __shared__ PC s_pc;
     __shared__ K s_keys[CHUNK];
     __shared__ uint32_t s_pay[CHUNK];
-    __shared__ uint32_t s_hist[kMaxPasses * kRadix];
+    __shared__ uint32_t s_hist[kRows * kRadix];
     __shared__ unsigned long long s_data;
-    for (int i = threadIdx.x; i < a.passes * kRadix; i += BLOCK) s_hist[i] = 0;
+    __shared__ uint64_t s_scan[BLOCK / kWave];
+    __shared__ uint64_t s_cdst[kMaxClasses];  // destination of the chunk's first slot of each class, minus its run start
+    __shared__ uint32_t s_chunk;
+    const int rows = CLS ? a.hist_rows : a.passes;
+    for (int i = threadIdx.x; i < rows * kRadix; i += BLOCK) s_hist[i] = 0;
     if (threadIdx.x == 0) s_data = 0;
     uint32_t my_data = 0;
     const bool with_inst = a.inst_s != nullptr;
     // the two most significant digits of the node keys are skewed toward 0
     const int peel_from = a.passes > 2 ? a.passes - 2 : 0;
+    // per class: first histogram row (bits 0-7) and passes (bits 8-15), in
+    // a register, so that a lane's class selects them without memory access
+    uint64_t cls_info = 0;
+#pragma unroll
+    for (int q = 0; q < kMaxClasses; ++q)
+        cls_info |= (uint64_t)((uint32_t)a.cls_row0[q] | ((uint32_t)a.cls_passes[q] << 8)) << (16 * q);
 
     const uint64_t nchunks = (a.E + CHUNK - 1) / CHUNK;
-    for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    for (;;) {
+        __syncthreads();  // previous chunk done with LDS
+        if (threadIdx.x == 0) s_chunk = atomicAdd(a.ticket, 1u);
+        __syncthreads();
+        const uint64_t c = s_chunk;
+        if (c >= nchunks) break;
         const uint64_t o0 = c * CHUNK;
         const uint64_t o1 = (o0 + CHUNK < a.E) ? o0 + CHUNK : a.E;
         const uint32_t klo = a.chunk_k[c];
@@ -356,7 +579,6 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(EmitArgs a, K *__restrict__
         const uint32_t npts = khi - klo + 1;
         const bool cached = npts <= (uint32_t)PC::kCap;
         const uint64_t obase = a.off[klo];
-        __syncthreads();  // previous chunk done with LDS
         if (cached) {
             for (uint32_t i = threadIdx.x; i <= npts; i += BLOCK) s_pc.off[i] = (uint32_t)(a.off[klo + i] - obase);
             for (uint32_t i = threadIdx.x; i < npts; i += BLOCK) {
@@ -370,6 +592,7 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(EmitArgs a, K *__restrict__
         auto offr = [&](uint32_t i) -> uint32_t {
             return cached ? s_pc.off[i] : (uint32_t)(a.off[klo + i] - obase);
         };
+        const uint32_t nrec = (uint32_t)(o1 - o0);
 
         const uint64_t r0 = o0 + (uint64_t)threadIdx.x * ITEMS;
         PointWalk<NAX> pw;
@@ -387,14 +610,65 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(EmitArgs a, K *__restrict__
             left = offr(idx + 1) - offr(idx) - t;  // records left in this point
             pw.seek(t);
         }
+
+        // With classes: this thread's records per class, from its points
+        // (before they are produced), scanned over the block.  That gives
+        // each record's slot in the class-split staging and the chunk's
+        // counts, which are published at once so that later chunks can look
+        // past this one while its records are still being produced.
+        uint64_t mine = 0, tot = 0, expect = 0;
+        if constexpr (CLS) {
+            if (r0 < o1) {
+                uint32_t need = (uint32_t)((o1 - r0) < (uint64_t)ITEMS ? (o1 - r0) : (uint64_t)ITEMS);
+                uint32_t k = idx, ta = offr(idx + 1) - offr(idx) - left;
+                while (need) {
+                    const uint32_t pcnt = offr(k + 1) - offr(k);
+                    const uint32_t tb = (pcnt - ta < need) ? pcnt : ta + need;
+                    if (tb > ta) {
+                        uint32_t rk[NAX > 0 ? NAX : 1];
+                        uint32_t pay;
+                        if (cached) {
+                            pay = s_pc.pay[k];
+#pragma unroll
+                            for (int ax = 0; ax < NAX; ++ax) rk[ax] = s_pc.rank[ax][k];
+                        } else {
+                            pay = a.pay[klo + k];
+#pragma unroll
+                            for (int ax = 0; ax < NAX; ++ax) rk[ax] = a.rs[(uint64_t)ax * a.n + klo + k];
+                        }
+                        expect += point_class_counts<NAX>(a, pay, rk, ta, tb);
+                        need -= tb - ta;
+                    }
+                    ++k;
+                    ta = 0;
+                }
+            }
+            mine = block_excl_sum_packed<BLOCK>(expect, s_scan, &tot);
+            if (threadIdx.x < (unsigned)a.ncls) {
+                const int q = threadIdx.x;
+                store_agent(&a.cls_status[c * kMaxClasses + q],
+                            DW::make(c == 0 ? kFlagInclusive : kFlagAggregate, (uint32_t)(tot >> (16 * q)) & 0xffffu));
+            }
+        }
+
+        uint64_t seen = 0;  // records produced per class (checked against the expectation)
 #pragma unroll 1
         for (int j = 0; j < ITEMS; ++j) {
             const bool valid = r0 + j < o1;
             K key = 0;
             if (valid) {
                 key = pw.template key<K>(a.inst_shift, with_inst, a.field_shift);
-                s_keys[threadIdx.x * ITEMS + j] = key;
-                s_pay[threadIdx.x * ITEMS + j] = pw.payload;
+                uint32_t lp = threadIdx.x * ITEMS + j;
+                if constexpr (CLS) {
+                    const int q = key_class(key, a.cls_c0);
+                    lp = packed_prefix(tot, q) + ((uint32_t)(mine >> (16 * q)) & 0xffffu);
+                    mine += 1ull << (16 * q);
+                    seen += 1ull << (16 * q);
+                }
+                if (lp < (uint32_t)CHUNK) {
+                    s_keys[lp] = key;
+                    s_pay[lp] = pw.payload;
+                }
                 my_data += pw.isq ? 0u : 1u;
                 if (--left) {
                     pw.next();
@@ -407,18 +681,79 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(EmitArgs a, K *__restrict__
                     pw.load(a, &s_pc, cached, klo, idx);
                 }
             }
-            hist_add(s_hist, key, valid, a.passes, peel_from);
+            if constexpr (!CLS) {
+                hist_add(s_hist, key, valid, a.passes, peel_from);
+            } else {
+                const int q = valid ? key_class(key, a.cls_c0) : 0;
+                const uint32_t ci = (uint32_t)(cls_info >> (16 * q));
+                hist_add_rows(s_hist, key, valid, (int)(ci & 0xffu), (int)((ci >> 8) & 0xffu), a.passes);
+            }
+        }
+        if constexpr (CLS) {
+            if (seen != expect) atomicOr(a.error, 1u);  // records disagree with the class counts: reported
+            // Class offsets from the chunks before this one, by wavefront 0
+            // after its share of the records (by then the chunks before have
+            // mostly published inclusive words): lane 16 q + k reads chunk
+            // hi - k for class q, 16 chunks per class per round trip; a
+            // class's walk ends at the nearest inclusive word (chunk 0
+            // publishes one at once).
+            if (threadIdx.x < kWave) {
+                const int lane = threadIdx.x, q = lane >> 4, k = lane & 15;
+                const bool act = q < a.ncls;
+                const uint32_t count = act ? ((uint32_t)(tot >> (16 * q)) & 0xffffu) : 0u;
+                unsigned long long *st = a.cls_status;
+                uint64_t excl = 0;
+                bool done = !act || c == 0;
+                int64_t hi = (int64_t)c - 1;
+                while (__ballot(!done)) {
+                    const int64_t t = hi - k;
+                    unsigned long long w = 0;
+                    if (!done && t >= 0) {
+                        while (DW::flag(w = load_agent(&st[(uint64_t)t * kMaxClasses + q])) == 0)
+                            __builtin_amdgcn_s_sleep(2);
+                    }
+                    const uint64_t im = __ballot(!done && t >= 0 && DW::flag(w) == kFlagInclusive);
+                    const uint32_t gm = (uint32_t)(im >> (16 * q)) & 0xffffu;
+                    const int k0 = gm ? __ffs(gm) - 1 : 15;  // nearest inclusive chunk of the class
+                    const uint64_t v = row_sum_u64((!done && t >= 0 && k <= k0) ? (uint64_t)(w & DW::kMask) : 0ull);
+                    if (!done) {
+                        excl += v;
+                        done = gm != 0;
+                        hi -= 16;
+                    }
+                }
+                if (act && k == 0) {
+                    if (c > 0) store_agent(&st[c * kMaxClasses + q], DW::make(kFlagInclusive, excl + count));
+                    s_cdst[q] = a.cls_base[q] + excl - packed_prefix(tot, q);
+                }
+            }
         }
         __syncthreads();
-        for (int i = threadIdx.x; i < CHUNK; i += BLOCK) {
-            if (o0 + i < o1) {
-                keys_out[o0 + i] = s_keys[i];
-                vals_out[o0 + i] = s_pay[i];
+        if constexpr (!CLS) {
+            for (uint32_t i = threadIdx.x; i < nrec; i += BLOCK) {
+                keys_a[o0 + i] = s_keys[i];
+                vals_a[o0 + i] = s_pay[i];
+            }
+        } else {
+            for (uint32_t i = threadIdx.x; i < nrec; i += BLOCK) {
+                int q = 0;
+#pragma unroll
+                for (int t = 1; t < kMaxClasses; ++t)
+                    if (t < a.ncls && i >= packed_prefix(tot, t)) q = t;
+                const uint64_t dst = s_cdst[q] + i;
+                if (dst >= a.E) continue;  // only if the class totals were wrong
+                if ((cls_info >> (16 * q + 8)) & 1u) {
+                    keys_a[dst] = s_keys[i];
+                    vals_a[dst] = s_pay[i];
+                } else {
+                    keys_b[dst] = s_keys[i];
+                    vals_b[dst] = s_pay[i];
+                }
             }
         }
     }
     __syncthreads();
-    hist_flush(s_hist, a.hist_part, a.passes);
+    hist_flush(s_hist, a.hist_part, rows);
     if (my_data) atomicAdd(&s_data, (unsigned long long)my_data);
     __syncthreads();
     if (threadIdx.x == 0 && s_data) atomicAdd(a.data_records, s_data);
@@ -481,7 +816,8 @@ struct Monoid {
 // records before it in its segment, i.e. over the data points that share
 // this tuple and lie strictly below it on the last axis.  Each such partial
 // goes to part[slot * nQ + query] (slot mode) or is F-combined atomically
-// into out[query] (atomic mode, for very sparse slot tables).
+// into out[query] (atomic mode, for very sparse slot tables).  Payloads and
+// w use the internal numbering of the points.
 template <class K, class W, class Acc, int OP>
 struct ForwardProblem {
     using V = Acc;
@@ -524,8 +860,8 @@ struct ForwardProblem {
 // grad_out over the queries after it in its segment, i.e. the queries sharing
 // the tuple and lying strictly above it on the last axis (equal last
 // coordinates put queries first, so they come before the data record and are
-// not counted).  Those partials go to part[slot * nD + data row], or are
-// summed atomically into grad[data row].
+// not counted).  Those partials go to part[slot * nD + data position], or
+// are summed atomically into grad[data position] (internal numbering).
 template <class K, class G>
 struct BackwardProblem {
     using V = G;
@@ -568,6 +904,7 @@ struct BackwardProblem {
 // digits of the point's ranks equal `digit` (1 for queries, 0 for data) and
 // lie below the instance's widths.
 struct RegroupArgs {
+    const uint32_t *inv;           // [nout]: output index of row o, or null (identity)
     const uint32_t *rank;          // [nax][n] by point slot
     const uint32_t *inst_of_slot;  // [n] or null
     const uint8_t *ltab;           // [nax][n_inst]
@@ -619,7 +956,7 @@ __global__ __launch_bounds__(256) void regroup_kernel(RegroupArgs a, const V *__
                 }
             }
         }
-        out[o] = acc;
+        out[a.inv ? a.inv[o] : o] = acc;
     }
 }
 

@@ -117,3 +117,53 @@ def test_python_front_end_fails_loudly_without_library(tmp_path):
     from paper_2305_16751_amd import binding
     with pytest.raises(RuntimeError, match="has not been built"):
         binding.load(str(tmp_path / "missing.so"))
+
+
+def test_plan_info_layout_matches_header(B, tmp_path):
+    """The ctypes mirror of dom_agg_plan_info has the C struct's size and
+    field offsets (compiled from the header with the host C compiler)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    fields = [f for f, _ in B.PlanInfo._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text(
+        "#include <stddef.h>\n#include <stdio.h>\n#include \"dom_agg.h\"\n"
+        "int main(void) {\n"
+        "  printf(\"size %zu\\n\", sizeof(dom_agg_plan_info));\n"
+        + "".join(f"  printf(\"{f} %zu\\n\", offsetof(dom_agg_plan_info, {f}));\n" for f in fields)
+        + "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                       check=True).stdout.splitlines())
+    assert int(got["size"]) == ctypes.sizeof(B.PlanInfo)
+    for f in fields:
+        assert int(got[f]) == getattr(B.PlanInfo, f).offset, f
+
+
+def test_no_kernel_uses_scratch_memory():
+    """Every kernel keeps its per-lane state in registers and LDS: the
+    compiler's resource report shows no scratch (private) memory."""
+    import subprocess
+    import sys
+    sys.path.insert(0, ROOT)
+    from paper_2305_16751_amd import build as bld
+    out = os.path.join(ROOT, "_build", "scratch_check.so")
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    r = subprocess.run(bld.compile_command(out, ["-Rpass-analysis=kernel-resource-usage"]),
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-2000:]
+    kernels, cur = {}, None
+    for line in r.stderr.splitlines():
+        m = re.search(r"remark:\s+(Function Name|ScratchSize \[bytes/lane\]): (\S+)", line)
+        if not m:
+            continue
+        if m.group(1) == "Function Name":
+            cur = m.group(2)
+        else:
+            kernels[cur] = int(m.group(2))
+    assert kernels, "no resource remarks"
+    assert not {k: v for k, v in kernels.items() if v}, "kernels with scratch"

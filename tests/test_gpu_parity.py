@@ -249,3 +249,53 @@ def test_atomic_regroup_path_m4():
              oracle.transposed_sum(4, c.D, c.Q, np.abs(g.astype(np.float64))), "atomic grad")
     check_fp(p.forward(to_dev(wf), "sum"), oracle.construction(4, c.D, c.Q, wf.astype(np.float64), "sum"),
              oracle.construction(4, c.D, c.Q, np.abs(wf.astype(np.float64)), "sum"), "atomic f32 sum")
+
+
+# ---------------------------------------------------------------------------
+# key-length classes of the record sort, internal numbering in batches
+
+
+@pytest.mark.parametrize("m,n,alpha", [(2, 20000, 1 << 20), (2, 3000, 300), (3, 6000, 1 << 20), (4, 1500, 1 << 20)])
+def test_sort_classes(m, n, alpha):
+    """Keys wider than one digit split the record sort into classes; every
+    class region must hold exactly its records, sorted."""
+    c = workloads.small_case(300 + m, m, n, n + 5, alphabet=alpha, coord="int", weight="int64")
+    p, _ = _run_and_check(c, "sum", np.int64)
+    info = p.info()
+    if info["key_bits"] > 8:
+        assert info["sort_classes"] >= 2, info
+    assert sum(info["sort_class_records"]) == info["records"], info
+    check_exact(p.forward(None, "count"), expected(m, c.D, c.Q, None, "count"), "count")
+    # recompute mode rebuilds the records from the stored class sizes
+    r = _plan(c, recompute=True)
+    check_exact(r.forward(to_dev(c.w), "sum"), oracle.construction(m, c.D, c.Q, c.w, "sum"), "recompute")
+
+
+@pytest.mark.parametrize("m", [2, 3])
+def test_small_batch_with_empty_instances(m):
+    """Uneven instances, some without data or queries: per-instance results
+    equal separate plans (internal numbering is per instance range)."""
+    from paper_2305_16751_amd import DomAggPlan
+    rng = np.random.default_rng(40 + m)
+    sizes_d = [0, 5, 300, 1, 0, 700, 64, 2]
+    sizes_q = [3, 0, 250, 0, 9, 650, 65, 1]
+    Ds, Qs, ws = [], [], []
+    for k, (nd, nq) in enumerate(zip(sizes_d, sizes_q)):
+        Ds.append(rng.integers(0, 50 + 40 * k, size=(nd, m), dtype=np.int32))
+        Qs.append(rng.integers(0, 50 + 40 * k, size=(nq, m), dtype=np.int32))
+        ws.append(rng.integers(0, 1000, size=nd).astype(np.int64))
+    D, Q, w = np.concatenate(Ds), np.concatenate(Qs), np.concatenate(ws)
+    doff = np.concatenate([[0], np.cumsum(sizes_d)]).astype(np.int64)
+    qoff = np.concatenate([[0], np.cumsum(sizes_q)]).astype(np.int64)
+    p = DomAggPlan(to_dev(D), to_dev(Q), doff, qoff)
+    out = p.forward(to_dev(w), "sum").cpu().numpy()
+    g = rng.standard_normal(Q.shape[0])
+    gw = p.backward(to_dev(g)).cpu().numpy()
+    for k in range(len(sizes_d)):
+        Dk, Qk, wk = Ds[k], Qs[k], ws[k]
+        if Qk.shape[0]:
+            check_exact(torch.from_numpy(out[qoff[k]:qoff[k + 1]]), oracle.construction(m, Dk, Qk, wk, "sum"),
+                        f"instance {k}")
+        if Dk.shape[0]:
+            want = oracle.transposed_sum(m, Dk, Qk, g[qoff[k]:qoff[k + 1]])
+            np.testing.assert_allclose(gw[doff[k]:doff[k + 1]], want, rtol=1e-12, atol=1e-9)
