@@ -3,7 +3,9 @@
 
 One step = the whole path on one batch of synthetic input: the coordinate
 phase (ranks, flat map, record sort) plus the forward segmented scan and
-regrouping, i.e. dom_agg_plan + dom_agg_forward, with inputs resident in HBM.
+regrouping, as one dom_agg_run call (the one-shot entry point, whose records
+carry the weights), with inputs resident in HBM.  The reusable-plan path
+(dom_agg_plan + dom_agg_forward) is timed too, as an extra.
 Default workload: m = 2, |D| = |Q| = 2^24 float32 coordinates U[0,1), float32
 weights N(0,1), F = sum (fp32 accumulation).
 
@@ -34,14 +36,18 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def key_bytes(info):
+def key_bytes(info, kernel=None):
+    """Bytes of a record key: from the record-sort kernel's name when given
+    (records that carry weights may use 64-bit keys for the query flag)."""
+    if kernel is not None:
+        return 8 if "_u64_" in kernel else 4
     return 4 if info["key_bits"] <= 32 else 8
 
 
-def record_sort_model(info):
+def record_sort_model(info, kernel=None):
     """Algorithmic bytes of the record sort and its number of digit passes:
     each pass reads and writes every record of its key-length class once."""
-    rb = key_bytes(info) + 4
+    rb = key_bytes(info, kernel) + 4
     ncls = info["sort_classes"]
     total, launches = 0, 0
     for c, ec in enumerate(info["sort_class_records"]):
@@ -58,7 +64,8 @@ def stage_table(kern, steps, info, n, nax, wbytes=4):
     E = info["records"]
     ED = info["data_records"]
     EQ = E - ED
-    kb = key_bytes(info)
+    rec = [k for k in kern if k.startswith("onesweep_records")]
+    kb = key_bytes(info, rec[0] if rec else None)
     model = {
         "flatmap_emit": E * (kb + 4) + n * (8 + 4 + 4 * nax),
         "forward_scan": E * (kb + 4) + ED * wbytes + EQ * wbytes,
@@ -71,7 +78,7 @@ def stage_table(kern, steps, info, n, nax, wbytes=4):
                "avg_ms_per_launch": round(avg, 5)}
         b = None
         if name.startswith("onesweep_records"):
-            tot, launches = record_sort_model(info)
+            tot, launches = record_sort_model(info, name)
             b = tot / max(launches, 1)
         elif name in model:
             b = model[name]
@@ -98,6 +105,28 @@ def time_steps(fn, steps, warmup):
     kern = binding.timing_read()
     binding.timing_enable(False)
     return (t1 - t0), kern
+
+
+def run_oneshot(case, steps, warmup, op="sum"):
+    """The headline step: one dom_agg_run call.  Plan info (sizes of the
+    flat map and its classes) comes from a plan of the same points built
+    outside the timed region."""
+    import torch
+    from paper_2305_16751_amd import DomAggPlan, dom_agg_run
+    d = torch.from_numpy(case.D).cuda()
+    q = torch.from_numpy(case.Q).cuda()
+    w = torch.from_numpy(case.w).cuda()
+    out = torch.empty(q.shape[0], dtype=torch.float32 if case.w.dtype == np.float32 else torch.int64,
+                      device="cuda")
+    p = DomAggPlan(d, q)
+    info = p.info()
+    p.close()
+
+    def step():
+        dom_agg_run(d, q, w, op, out=out)
+
+    T, kern = time_steps(step, steps, warmup)
+    return T, kern, info, out
 
 
 def run_plain(case, steps, warmup, op="sum"):
@@ -127,7 +156,7 @@ def roofline_entry(kern, info):
         return None
     name, (ms, cnt) = max(rec.items(), key=lambda kv: kv[1][0])
     avg_s = ms / cnt * 1e-3
-    tot, launches = record_sort_model(info)
+    tot, launches = record_sort_model(info, name)
     b = tot / launches
     ach = b / avg_s / 1e9
     return {"bound": "hbm", "kernel": name, "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -151,10 +180,19 @@ def cpu_baseline(n_sample=1 << 19):
                       f"fp64 sequential construction (Sec. 4 + Sec. 5), {dt:.2f} s"}
 
 
+def extra_plan_forward(case, steps):
+    """The reusable-plan path on the headline workload: dom_agg_plan +
+    dom_agg_forward (payloads are indices, the scan gathers the weights)."""
+    T, kern, info, _ = run_plain(case, steps, 2)
+    return {"workload": case.name, "value": round(case.n * steps / T, 1), "ms_per_step": round(T / steps * 1e3, 3),
+            "step": "dom_agg_plan + dom_agg_forward",
+            "stages": stage_table(kern, steps, info, case.n, case.m - 1)}
+
+
 def extra_m3(steps):
     import workloads
     c = workloads.f32_3d_1m()
-    T, kern, info, _ = run_plain(c, steps, 2)
+    T, kern, info, _ = run_oneshot(c, steps, 2)
     return {"workload": "f32_3d_1m", "value": round(c.n * steps / T, 1), "ms_per_step": round(T / steps * 1e3, 3),
             "records": info["records"], "key_bits": info["key_bits"],
             "stages": stage_table(kern, steps, info, c.n, 2)}
@@ -251,7 +289,7 @@ def main():
         del a, b
     case = workloads.f32_2d_16m()
     log(f"headline: {case.name} m={case.m} |D|={case.D.shape[0]} |Q|={case.Q.shape[0]}")
-    T, kern, info, _ = run_plain(case, args.steps, args.warmup)
+    T, kern, info, _ = run_oneshot(case, args.steps, args.warmup)
     value = case.n * args.steps / T
     log(f"headline: {T / args.steps * 1e3:.3f} ms/step, {value:.4g} (|D|+|Q|)/s, E={info['records']}")
     result = {
@@ -271,7 +309,7 @@ def main():
                    "n_query": int(case.Q.shape[0]), "op": "sum", "coords": "float32 U[0,1)",
                    "weights": "float32 N(0,1)", "records": info["records"], "key_bits": info["key_bits"],
                    "sort_passes": info["sort_passes"], "sort_classes": info["sort_classes"], "sort_tile": info["sort_tile"],
-                   "scan_tile": info["scan_tile"], "step": "dom_agg_plan + dom_agg_forward"},
+                   "scan_tile": info["scan_tile"], "step": "dom_agg_run (plan + forward in one call)"},
         "roofline": roofline_entry(kern, info),
     }
     extra = {"stages": stage_table(kern, args.steps, info, case.n, case.m - 1)}
@@ -279,8 +317,8 @@ def main():
         log("cpu baseline (oracle on a sample) ...")
         result["cpu_baseline"] = cpu_baseline(args.cpu_sample)
     if not args.no_extras:
-        for name, fn in (("m3", lambda: extra_m3(5)), ("fwd_bwd", lambda: extra_fwd_bwd(5)),
-                         ("batched", lambda: extra_batched(3))):
+        for name, fn in (("plan_forward", lambda: extra_plan_forward(case, 5)), ("m3", lambda: extra_m3(5)),
+                         ("fwd_bwd", lambda: extra_fwd_bwd(5)), ("batched", lambda: extra_batched(3))):
             log(f"extra: {name} ...")
             try:
                 extra[name] = fn()

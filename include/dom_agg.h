@@ -184,6 +184,32 @@ dom_agg_status dom_agg_forward(dom_agg_plan_t plan, dom_agg_op op, dom_agg_dtype
 dom_agg_status dom_agg_backward(dom_agg_plan_t plan, dom_agg_dtype grad_dtype,
                                 const void *grad_out, void *grad_weights, void *stream);
 
+/*
+ * One-shot forward: dom_agg_plan + dom_agg_forward in one call, for callers
+ * that need no plan afterwards (no backward, no second forward).  The
+ * records of the flat map carry the weights themselves, as the expanded list
+ * of the construction does (Sec. 4: each element of the union carries its
+ * weight; Sec. 5), so the segmented scan reads them in sequence instead of
+ * gathering them; query records are told apart by a flag bit above every key
+ * digit the sort reads.  This holds for weight dtypes of 4 bytes (I32, F32)
+ * and for COUNT, when m >= 2 and the record key leaves room for the flag;
+ * otherwise the call runs a plan + forward internally.  Same results as
+ * plan + forward (integer results and MAX exact, fp sums to rounding order).
+ *
+ *   m, coord_dtype, d_coords, q_coords, n_inst, d_offsets, q_offsets: as
+ *       for dom_agg_plan;
+ *   op, weight_dtype, weights, out: as for dom_agg_forward;
+ *   flags    0 or DOM_AGG_NO_TUNE.
+ *   stream   hipStream_t; the call synchronises with it while it sizes the
+ *            flat map, and returns with the scan and the regrouping enqueued.
+ *
+ * Errors: those of dom_agg_plan and dom_agg_forward.
+ */
+dom_agg_status dom_agg_run(int m, dom_agg_dtype coord_dtype, const void *d_coords,
+                           const void *q_coords, int64_t n_inst, const int64_t *d_offsets,
+                           const int64_t *q_offsets, dom_agg_op op, dom_agg_dtype weight_dtype,
+                           const void *weights, void *out, uint32_t flags, void *stream);
+
 /* Sizes of a plan.  info (host) is filled on success. */
 dom_agg_status dom_agg_plan_get_info(dom_agg_plan_t plan, dom_agg_plan_info *info);
 

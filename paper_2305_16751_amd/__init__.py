@@ -5,4 +5,4 @@ the Sec. 5 improvement) as hand-written HIP kernels behind the C-ABI of
 include/dom_agg.h; this package is its PyTorch front end.
 """
 from .binding import DomAggError  # noqa: F401
-from .dom_agg import DomAggFunction, DomAggPlan, dom_agg, dom_agg_batched  # noqa: F401
+from .dom_agg import DomAggFunction, DomAggPlan, dom_agg, dom_agg_batched, dom_agg_run  # noqa: F401

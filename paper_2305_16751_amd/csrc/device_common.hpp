@@ -108,6 +108,22 @@ __device__ __forceinline__ void publish_status(uint64_t *st, uint32_t tile, uint
     }
 }
 
+// One read of a tile's status: its flag (0 = not yet published) and value.
+template <class V>
+__device__ __forceinline__ uint32_t try_status(const uint64_t *st, uint32_t tile, V &v) {
+    if constexpr (sizeof(V) == 4) {
+        const uint64_t w = load_agent(st + tile);
+        v = from_bits<V>(w & 0xffffffffull);
+        return (uint32_t)(w >> 32);
+    } else {
+        const uint64_t w0 = load_agent(st + 2ull * tile);
+        const uint64_t w1 = load_agent(st + 2ull * tile + 1);
+        const uint32_t f0 = (uint32_t)(w0 >> 32), f1 = (uint32_t)(w1 >> 32);
+        v = from_bits<V>((w0 & 0xffffffffull) | (w1 << 32));
+        return f0 == f1 ? f0 : 0u;
+    }
+}
+
 // Spins until the tile's status is published; returns its flag and value.
 template <class V>
 __device__ __forceinline__ uint32_t wait_status(const uint64_t *st, uint32_t tile, V &v) {
@@ -237,6 +253,20 @@ __device__ __forceinline__ uint64_t read_lane_u64(uint64_t v, int src) {
     const uint32_t lo = read_lane_u32((uint32_t)v, src);
     const uint32_t hi = read_lane_u32((uint32_t)(v >> 32), src);
     return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+// Value of `v` at a lane index that is the same for the whole wavefront
+// (v_readlane into a scalar register: no LDS round trip).
+template <class V>
+__device__ __forceinline__ V read_uniform_lane(V v, int src) {
+    if constexpr (sizeof(V) == 4) {
+        return from_bits<V>((uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)to_bits(v), src));
+    } else {
+        const uint64_t b = to_bits(v);
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, src);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), src);
+        return from_bits<V>((uint64_t)lo | ((uint64_t)hi << 32));
+    }
 }
 
 template <class V>

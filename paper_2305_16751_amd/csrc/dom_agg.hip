@@ -284,6 +284,13 @@ struct dom_agg_plan_s {
     // each data / query position, and a buffer for inputs in that order
     bool permuted = false;
     DevBuf dinv, qinv, perm;
+    // records carrying weights (one-shot calls): requested, granted, the
+    // query flag's bit in the record key, the weights and their dtype
+    bool inline_req = false, inline_w = false;
+    int flag_shift = -1;
+    const void *w_src = nullptr;
+    dom_agg_dtype w_dt = DOM_AGG_F32;
+    DevBuf rw, wv;
     // regrouping: level-tuple slots (slot mode) or atomic F
     uint32_t n_slots = 1;
     bool use_slots = true;
@@ -302,7 +309,7 @@ struct dom_agg_plan_s {
 
     size_t workspace() const {
         return off.bytes + rs.bytes + pay.bytes + inst_s.bytes + rank.bytes + inst_of_slot.bytes + ltab.bytes +
-               dinv.bytes + qinv.bytes + perm.bytes + part.bytes + rkeys.bytes + rvals.bytes + scan_status.bytes + scan_ticket.bytes + ed_counter.bytes;
+               dinv.bytes + qinv.bytes + perm.bytes + rw.bytes + wv.bytes + part.bytes + rkeys.bytes + rvals.bytes + scan_status.bytes + scan_ticket.bytes + ed_counter.bytes;
     }
     SlotMap slot_map() const {
         SlotMap sm{};
@@ -366,6 +373,7 @@ const char *onesweep_name(int tile) {
          {"onesweep_points_u64_t2048", "onesweep_points_u64_t4096", "onesweep_points_u64_t8192"}},
         {{"onesweep_records_u32_t2048", "onesweep_records_u32_t4096", "onesweep_records_u32_t8192"},
          {"onesweep_records_u64_t2048", "onesweep_records_u64_t4096", "onesweep_records_u64_t8192"}}};
+    if (tile == 16384) return sizeof(K) == 8 ? "onesweep_records_u64_t16384" : "onesweep_records_u32_t16384";
     const int ti = tile == 2048 ? 0 : tile == 4096 ? 1 : 2;
     return names[ROLE][sizeof(K) == 8][ti];
 }
@@ -383,13 +391,27 @@ void onesweep_launch(const K *kin, const uint32_t *vin, K *kout, uint32_t *vout,
     });
 }
 
+// The tile a sort pass really uses (16384 only for the record sort with
+// 32-bit keys; its 64-bit-key form would not fit the registers).
+template <class K, int ROLE>
+int effective_tile(int tile) {
+    if (!valid_sort_tile(tile)) return 4096;
+    if (tile == 16384 && (ROLE != 1 || sizeof(K) != 4)) return 8192;
+    return tile;
+}
+
 template <class K, class S, int ROLE>
 void onesweep_dispatch(int tile, const K *kin, const uint32_t *vin, K *kout, uint32_t *vout, uint32_t n,
                        int shift, const uint32_t *bases, void *status, uint32_t *ticket, hipStream_t s) {
     S *st = static_cast<S *>(status);
     if (tile == 2048) onesweep_launch<K, S, 256, 8, ROLE>(kin, vin, kout, vout, n, shift, bases, st, ticket, s);
     else if (tile == 8192) onesweep_launch<K, S, 512, 16, ROLE>(kin, vin, kout, vout, n, shift, bases, st, ticket, s);
-    else onesweep_launch<K, S, 256, 16, ROLE>(kin, vin, kout, vout, n, shift, bases, st, ticket, s);
+    else if (tile == 16384) {
+        if constexpr (ROLE == 1 && sizeof(K) == 4)
+            onesweep_launch<K, S, 512, 32, ROLE>(kin, vin, kout, vout, n, shift, bases, st, ticket, s);
+        else
+            fail(DOM_AGG_EHIP, "internal: no 16384-element tile for this sort");
+    } else onesweep_launch<K, S, 256, 16, ROLE>(kin, vin, kout, vout, n, shift, bases, st, ticket, s);
 }
 
 // Sorts (kA, vA) by the listed digit shifts; returns true when the result
@@ -398,7 +420,7 @@ template <class K, int ROLE>
 bool radix_sort(K *kA, uint32_t *vA, K *kB, uint32_t *vB, uint64_t n, const std::vector<int> &shifts,
                 const uint32_t *bases, int tile, hipStream_t s) {
     if (n == 0 || shifts.empty()) return false;
-    if (!valid_sort_tile(tile)) tile = 4096;
+    tile = effective_tile<K, ROLE>(tile);
     const bool narrow = n < (1ull << 30);  // every digit count fits 30 bits
     DevBuf status, ticket;
     status.alloc(ceil_div(n, tile) * kRadix * (narrow ? 4 : 8) + 8, s);
@@ -545,6 +567,8 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
             rp.slots = sv.as<uint32_t>();
             rp.rank = rank.as<uint32_t>();
             rp.kcount = kcount.as<uint32_t>();
+            rp.n = n;
+            rp.n_inst = (uint32_t)ni;
             rp.nQ = nQ;
             rp.doff = P->batched ? doff_dev.as<int64_t>() : nullptr;
             rp.qoff = P->batched ? qoff_dev.as<int64_t>() : nullptr;
@@ -556,7 +580,7 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
                 scan_ticket.as<uint32_t>(), s);
         } else if (axis < nax) {
             RankProblem<KP> rp{sk.as<KP>(), sv.as<uint32_t>(), rank.as<uint32_t>() + (size_t)axis * n,
-                               kcount.as<uint32_t>() + (size_t)axis * ni};
+                               kcount.as<uint32_t>() + (size_t)axis * ni, n, (uint32_t)ni};
             scan_launch<RankProblem<KP>, sizeof(KP) == 4 ? 16 : 8>(
                 "rank_scan", rp, n, scan_status.as<uint64_t>(), scan_status.bytes / 8,
                 scan_ticket.as<uint32_t>(), s);
@@ -591,6 +615,15 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
     P->key_bits = sum + (P->batched ? P->inst_bits : 0);
     if (P->key_bits > 64) fail(DOM_AGG_ETOOBIG, "record sort key needs %d bits (> 64)", P->key_bits);
     P->key64 = P->key_bits > 32;
+    if (P->inline_req && nax > 0) {
+        // the query flag goes one bit above the digits the record sort reads
+        const int fs = kRadixBits * std::max(1, (int)ceil_div(P->key_bits, kRadixBits));
+        if (fs < 64) {
+            P->inline_w = true;
+            P->flag_shift = fs;
+            P->key64 = fs >= 32;
+        }
+    }
     // Key-length classes (one instance only: the instance bits of a batch sit
     // above every node id, so nearly all keys would share one class).
     if (!P->batched && nax >= 1) {
@@ -632,15 +665,36 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
     P->pay.alloc((size_t)n * 4, s);
     if (P->batched) P->inst_s.alloc((size_t)n * 4, s);
 
+    if (P->inline_w) {
+        // first-axis rank and weight bits side by side: the count scan's one
+        // gather per point fetches both
+        P->rw.alloc((size_t)n * 8, s);
+        P->wv.alloc((size_t)n * 4, s);
+        launch("pack_rank_weight", s, [&] {
+            if (P->w_dt == DOM_AGG_I32)
+                pack_rank_weight_kernel<int32_t><<<grid_for(n), kBlock, 0, s>>>(
+                    rank.as<uint32_t>(), P->dinv.as<uint32_t>(), static_cast<const int32_t *>(P->w_src), nQ, n,
+                    P->rw.as<uint64_t>());
+            else
+                pack_rank_weight_kernel<float><<<grid_for(n), kBlock, 0, s>>>(
+                    rank.as<uint32_t>(), P->dinv.as<uint32_t>(), static_cast<const float *>(P->w_src), nQ, n,
+                    P->rw.as<uint64_t>());
+        });
+    }
     auto count = [&](auto nax_c) {
         constexpr int NAX = decltype(nax_c)::value;
-        CountProblem<KP, NAX> cp{sig_keys.as<KP>(), sig_slots.as<uint32_t>(), rank.as<uint32_t>(),
-                                 P->ltab.as<uint8_t>(), (uint32_t)ni, nQ, n,
-                                 P->off.as<uint64_t>(), P->rs.as<uint32_t>(), P->pay.as<uint32_t>(),
-                                 P->inst_s.as<uint32_t>()};
-        scan_launch<CountProblem<KP, NAX>, sizeof(KP) == 4 ? 16 : 8>(
-            "count_scan", cp, n, scan_status.as<uint64_t>(), scan_status.bytes / 8,
-            scan_ticket.as<uint32_t>(), s);
+        auto go = [&](auto inl_c) {
+            constexpr bool INL = decltype(inl_c)::value;
+            CountProblem<KP, NAX, INL> cp{sig_keys.as<KP>(), sig_slots.as<uint32_t>(), rank.as<uint32_t>(),
+                                          P->ltab.as<uint8_t>(), (uint32_t)ni, nQ, n,
+                                          P->off.as<uint64_t>(), P->rs.as<uint32_t>(), P->pay.as<uint32_t>(),
+                                          P->inst_s.as<uint32_t>(), P->rw.as<uint64_t>(), P->wv.as<uint32_t>()};
+            scan_launch<CountProblem<KP, NAX, INL>, sizeof(KP) == 4 ? 16 : 8>(
+                "count_scan", cp, n, scan_status.as<uint64_t>(), scan_status.bytes / 8,
+                scan_ticket.as<uint32_t>(), s);
+        };
+        if (NAX > 0 && P->inline_w) go(std::true_type{});
+        else go(std::false_type{});
     };
     switch (nax) {
         case 0: count(std::integral_constant<int, 0>{}); break;
@@ -711,6 +765,8 @@ void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &ou
     a.passes = passes;
     a.hist_part = part.as<uint32_t>();
     a.data_records = P->ed_counter.as<unsigned long long>();
+    a.wv = P->inline_w ? P->wv.as<uint32_t>() : nullptr;
+    a.flag_shift = P->inline_w ? P->flag_shift : -1;
     a.ncls = P->ncls;
     a.cls_c0 = P->cls_c0;
     a.hist_rows = rows;
@@ -904,13 +960,15 @@ void scatter(const T *src, const uint32_t *idx, T *dst, uint64_t n, hipStream_t 
     launch("permute_out", s, [&] { scatter_kernel<T><<<grid_for(n), kBlock, 0, s>>>(src, idx, dst, n); });
 }
 
-template <class K, class W, class V, int OP>
-void forward_typed(Plan *P, const void *kp, const uint32_t *vp, const void *w, void *out, hipStream_t s) {
-    ForwardProblem<K, W, V, OP> fp{};
+template <class K, class W, class V, int OP, bool INL>
+void forward_run(Plan *P, const void *kp, const uint32_t *vp, const void *w, void *out, hipStream_t s) {
+    ForwardProblem<K, W, V, OP, INL> fp{};
     fp.keys = static_cast<const K *>(kp);
     fp.vals = vp;
     fp.w = static_cast<const W *>(w);
-    if constexpr (OP != OP_COUNT) {
+    fp.flag_shift = P->flag_shift;
+    fp.nw = (uint64_t)P->nD;
+    if constexpr (OP != OP_COUNT && !INL) {
         if (P->permuted && P->nD > 0) {
             gather(static_cast<const W *>(w), P->dinv.as<uint32_t>(), P->perm.as<W>(), (uint64_t)P->nD, s);
             fp.w = P->perm.as<W>();
@@ -927,16 +985,26 @@ void forward_typed(Plan *P, const void *kp, const uint32_t *vp, const void *w, v
         fp.out = P->permuted ? P->part.as<V>() : res;
         fill(fp.out, (uint64_t)P->nQ, host_identity<V, OP>(), s);
     }
+    using FP = ForwardProblem<K, W, V, OP, INL>;
     if (P->tune.scan_items == 8 || sizeof(K) == 8)
-        scan_launch<ForwardProblem<K, W, V, OP>, 8>("forward_scan", fp, (uint64_t)P->E,
-                                                    P->scan_status.as<uint64_t>(), P->scan_words,
-                                                    P->scan_ticket.as<uint32_t>(), s);
+        scan_launch<FP, 8>("forward_scan", fp, (uint64_t)P->E, P->scan_status.as<uint64_t>(), P->scan_words,
+                           P->scan_ticket.as<uint32_t>(), s);
     else
-        scan_launch<ForwardProblem<K, W, V, OP>, 16>("forward_scan", fp, (uint64_t)P->E,
-                                                     P->scan_status.as<uint64_t>(), P->scan_words,
-                                                     P->scan_ticket.as<uint32_t>(), s);
+        scan_launch<FP, 16>("forward_scan", fp, (uint64_t)P->E, P->scan_status.as<uint64_t>(), P->scan_words,
+                            P->scan_ticket.as<uint32_t>(), s);
     if (P->use_slots && P->nax > 0) regroup<V, OP>(P, true, P->part.as<V>(), res, s);
     else if (!P->use_slots && P->permuted) scatter(P->part.as<V>(), P->qinv.as<uint32_t>(), res, (uint64_t)P->nQ, s);
+}
+
+// Records that carry weights were built for one (op, weight dtype); the
+// scan then reads the weights from the records.
+template <class K, class W, class V, int OP>
+void forward_typed(Plan *P, const void *kp, const uint32_t *vp, const void *w, void *out, hipStream_t s) {
+    if constexpr (OP == OP_COUNT || sizeof(W) == 4) {
+        if (P->inline_w) return forward_run<K, W, V, OP, true>(P, kp, vp, w, out, s);
+    }
+    if (P->inline_w) fail(DOM_AGG_EHIP, "internal: records carry 4-byte weights");
+    forward_run<K, W, V, OP, false>(P, kp, vp, w, out, s);
 }
 
 template <class K>
@@ -973,6 +1041,7 @@ void backward_typed(Plan *P, const void *kp, const uint32_t *vp, const void *g, 
     G *const res = static_cast<G *>(grad);
     bp.sm = P->slot_map();
     bp.stride = (uint64_t)P->nD;
+    bp.ng = (uint64_t)P->nQ;
     bp.E = (uint64_t)P->E;
     if (P->use_slots) {
         bp.part = P->nax == 0 ? res : P->part.as<G>();
@@ -1050,7 +1119,10 @@ float time_ms(hipStream_t s, const std::function<void()> &f) {
     return ms;
 }
 
-TuneKey tune_key(const Plan *P) { return TuneKey{P->m, P->key_bits, bits_for((uint64_t)P->E)}; }
+// (records carrying weights are tuned separately: their keys may be wider)
+TuneKey tune_key(const Plan *P) {
+    return TuneKey{P->m + (P->inline_w ? 16 : 0), P->key_bits, bits_for((uint64_t)P->E)};
+}
 
 // Applies a cached choice; called before the records are built, so that the
 // plan's own record sort runs with it.
@@ -1072,7 +1144,8 @@ void tune_plan(Plan *P, hipStream_t s) {
     // the per-point state is still present here (plan construction)
     float best = 1e30f;
     int best_tile = P->tune.record_sort_tile;
-    for (int tile : {2048, 4096, 8192}) {
+    for (int tile : {2048, 4096, 8192, 16384}) {
+        if (effective_tile<uint32_t, 1>(tile) != tile || (P->key64 && tile == 16384)) continue;
         P->tune.record_sort_tile = tile;
         DevBuf k, v;
         const float ms = time_ms(s, [&] {
@@ -1107,6 +1180,117 @@ void tune_plan(Plan *P, hipStream_t s) {
         P->tune.scan_items = best_scan;
     }
     tc.store(key, P->tune);
+}
+
+
+// Argument checks shared by dom_agg_plan and dom_agg_run (no HIP call).
+void check_plan_args(int m, dom_agg_dtype coord_dtype, const void *d_coords, const void *q_coords, int64_t n_inst,
+                     const int64_t *d_offsets, const int64_t *q_offsets) {
+    if (m < 1 || m > 4) fail(DOM_AGG_EINVAL, "m = %d is outside [1, 4]", m);
+    if (coord_dtype == DOM_AGG_F64 || coord_dtype == DOM_AGG_I64)
+        fail(DOM_AGG_EUNSUPPORTED, "coordinates must be float32 or int32");
+    if (coord_dtype != DOM_AGG_F32 && coord_dtype != DOM_AGG_I32)
+        fail(DOM_AGG_EINVAL, "unknown coordinate dtype %d", (int)coord_dtype);
+    if (n_inst < 1 || n_inst > (1ll << 30)) fail(DOM_AGG_EINVAL, "n_inst = %lld", (long long)n_inst);
+    if (!d_offsets || !q_offsets) fail(DOM_AGG_EINVAL, "offsets are NULL");
+    if (d_offsets[0] != 0 || q_offsets[0] != 0) fail(DOM_AGG_EINVAL, "offsets must start at 0");
+    for (int64_t k = 0; k < n_inst; ++k)
+        if (d_offsets[k + 1] < d_offsets[k] || q_offsets[k + 1] < q_offsets[k])
+            fail(DOM_AGG_EINVAL, "offsets decrease at instance %lld", (long long)k);
+    const int64_t nD = d_offsets[n_inst], nQ = q_offsets[n_inst];
+    if (nD > 0 && !d_coords) fail(DOM_AGG_EINVAL, "d_coords is NULL with %lld data points", (long long)nD);
+    if (nQ > 0 && !q_coords) fail(DOM_AGG_EINVAL, "q_coords is NULL with %lld queries", (long long)nQ);
+    if (nD + nQ > 0x7fffffffll) fail(DOM_AGG_ETOOBIG, "|D| + |Q| must be below 2^31");
+}
+
+void check_forward_args(dom_agg_op op, dom_agg_dtype weight_dtype, const void *weights, const void *out, int64_t nD,
+                        int64_t nQ) {
+    if (op != DOM_AGG_SUM && op != DOM_AGG_MAX && op != DOM_AGG_COUNT) fail(DOM_AGG_EINVAL, "unknown op %d", (int)op);
+    if (op != DOM_AGG_COUNT && (weight_dtype < DOM_AGG_I32 || weight_dtype > DOM_AGG_F64))
+        fail(DOM_AGG_EINVAL, "unknown weight dtype %d", (int)weight_dtype);
+    if (op != DOM_AGG_COUNT && nD > 0 && !weights) fail(DOM_AGG_EINVAL, "weights are NULL");
+    if (nQ > 0 && !out) fail(DOM_AGG_EINVAL, "out is NULL");
+}
+
+size_t value_bytes(dom_agg_op op, dom_agg_dtype wdt) {
+    const bool wide = op == DOM_AGG_COUNT || (op == DOM_AGG_SUM && wdt != DOM_AGG_F32) || wdt == DOM_AGG_I64 ||
+                      wdt == DOM_AGG_F64;
+    return wide ? 8 : 4;
+}
+
+// Builds a plan (validated arguments).  With inline_req, the records carry
+// the weights w (4-byte dtype, or none for COUNT) when the key leaves room
+// for the query flag.
+std::unique_ptr<Plan> make_plan(int m, dom_agg_dtype coord_dtype, const void *d_coords, const void *q_coords,
+                                int64_t n_inst, const int64_t *d_offsets, const int64_t *q_offsets, uint32_t flags,
+                                hipStream_t s, const void *w, dom_agg_dtype wdt, bool inline_req) {
+    const int64_t nD = d_offsets[n_inst], nQ = q_offsets[n_inst];
+    int dev;
+    require_gfx950(&dev);
+    auto P = std::make_unique<Plan>();
+    P->device = dev;
+    P->m = m;
+    P->nax = m - 1;
+    P->flags = flags;
+    P->n_inst = n_inst;
+    P->nD = nD;
+    P->nQ = nQ;
+    P->n = nD + nQ;
+    P->batched = n_inst > 1;
+    P->inst_bits = P->batched ? bits_for((uint64_t)n_inst) : 0;
+    P->tune = default_tune();
+    P->inline_req = inline_req;
+    P->w_src = w;
+    P->w_dt = wdt;
+    if (P->n > 0) {
+        HostStage hs;
+        DevBuf sig_keys, sig_slots;
+        if (coord_dtype == DOM_AGG_F32) {
+            if (P->batched)
+                build_points<float, uint64_t>(P.get(), (const float *)d_coords, (const float *)q_coords,
+                                              d_offsets, q_offsets, s, hs, sig_keys, sig_slots);
+            else
+                build_points<float, uint32_t>(P.get(), (const float *)d_coords, (const float *)q_coords,
+                                              d_offsets, q_offsets, s, hs, sig_keys, sig_slots);
+        } else {
+            if (P->batched)
+                build_points<int32_t, uint64_t>(P.get(), (const int32_t *)d_coords, (const int32_t *)q_coords,
+                                                d_offsets, q_offsets, s, hs, sig_keys, sig_slots);
+            else
+                build_points<int32_t, uint32_t>(P.get(), (const int32_t *)d_coords,
+                                                (const int32_t *)q_coords, d_offsets, q_offsets, s, hs,
+                                                sig_keys, sig_slots);
+        }
+        sig_keys.reset();
+        sig_slots.reset();
+        const uint64_t tiles = ceil_div((uint64_t)std::max<int64_t>(P->E, 1), kBlock * 8);
+        P->scan_words = tiles * 4;
+        P->scan_status.alloc(P->scan_words * 8, s);
+        P->scan_ticket.alloc(16, s);
+        if (P->E > 0) {
+            const bool tuned = !(flags & DOM_AGG_NO_TUNE) && tune_lookup(P.get());
+            DevBuf k, v;
+            if (P->key64) build_records<uint64_t>(P.get(), s, &hs, true, k, v);
+            else build_records<uint32_t>(P.get(), s, &hs, true, k, v);
+            P->rkeys = std::move(k);
+            P->rvals = std::move(v);
+            if (!(flags & DOM_AGG_NO_TUNE) && !tuned) tune_plan(P.get(), s);
+            if (flags & DOM_AGG_RECOMPUTE) {
+                P->rkeys.reset();
+                P->rvals.reset();
+            } else {
+                // the last-axis-ordered state is only needed to rebuild the records
+                P->rs.reset();
+                P->pay.reset();
+                P->inst_s.reset();
+                P->off.reset();
+                P->rw.reset();
+                P->wv.reset();
+            }
+        }
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    return P;
 }
 
 }  // namespace
@@ -1146,88 +1330,37 @@ dom_agg_status dom_agg_plan(dom_agg_plan_t *plan, int m, dom_agg_dtype coord_dty
                             const void *q_coords, int64_t n_inst, const int64_t *d_offsets,
                             const int64_t *q_offsets, uint32_t flags, void *stream) {
     return guarded([&] {
-        // ---- validation: no HIP call before this block completes ----
         if (!plan) fail(DOM_AGG_EINVAL, "plan is NULL");
-        if (m < 1 || m > 4) fail(DOM_AGG_EINVAL, "m = %d is outside [1, 4]", m);
-        if (coord_dtype == DOM_AGG_F64 || coord_dtype == DOM_AGG_I64)
-            fail(DOM_AGG_EUNSUPPORTED, "coordinates must be float32 or int32");
-        if (coord_dtype != DOM_AGG_F32 && coord_dtype != DOM_AGG_I32)
-            fail(DOM_AGG_EINVAL, "unknown coordinate dtype %d", (int)coord_dtype);
-        if (n_inst < 1 || n_inst > (1ll << 30)) fail(DOM_AGG_EINVAL, "n_inst = %lld", (long long)n_inst);
-        if (!d_offsets || !q_offsets) fail(DOM_AGG_EINVAL, "offsets are NULL");
-        if (d_offsets[0] != 0 || q_offsets[0] != 0) fail(DOM_AGG_EINVAL, "offsets must start at 0");
-        for (int64_t k = 0; k < n_inst; ++k)
-            if (d_offsets[k + 1] < d_offsets[k] || q_offsets[k + 1] < q_offsets[k])
-                fail(DOM_AGG_EINVAL, "offsets decrease at instance %lld", (long long)k);
-        const int64_t nD = d_offsets[n_inst], nQ = q_offsets[n_inst];
-        if (nD > 0 && !d_coords) fail(DOM_AGG_EINVAL, "d_coords is NULL with %lld data points", (long long)nD);
-        if (nQ > 0 && !q_coords) fail(DOM_AGG_EINVAL, "q_coords is NULL with %lld queries", (long long)nQ);
-        if (nD + nQ > 0x7fffffffll) fail(DOM_AGG_ETOOBIG, "|D| + |Q| must be below 2^31");
+        check_plan_args(m, coord_dtype, d_coords, q_coords, n_inst, d_offsets, q_offsets);
         if (flags & ~(uint32_t)(DOM_AGG_RECOMPUTE | DOM_AGG_GRAPH | DOM_AGG_NO_TUNE))
             fail(DOM_AGG_EINVAL, "unknown flags 0x%x", flags);
-        // ---- device work ----
-        int dev;
-        require_gfx950(&dev);
-        hipStream_t s = static_cast<hipStream_t>(stream);
-        auto P = std::make_unique<Plan>();
-        P->device = dev;
-        P->m = m;
-        P->nax = m - 1;
-        P->flags = flags;
-        P->n_inst = n_inst;
-        P->nD = nD;
-        P->nQ = nQ;
-        P->n = nD + nQ;
-        P->batched = n_inst > 1;
-        P->inst_bits = P->batched ? bits_for((uint64_t)n_inst) : 0;
-        P->tune = default_tune();
-        if (P->n > 0) {
-            HostStage hs;
-            DevBuf sig_keys, sig_slots;
-            if (coord_dtype == DOM_AGG_F32) {
-                if (P->batched)
-                    build_points<float, uint64_t>(P.get(), (const float *)d_coords, (const float *)q_coords,
-                                                  d_offsets, q_offsets, s, hs, sig_keys, sig_slots);
-                else
-                    build_points<float, uint32_t>(P.get(), (const float *)d_coords, (const float *)q_coords,
-                                                  d_offsets, q_offsets, s, hs, sig_keys, sig_slots);
-            } else {
-                if (P->batched)
-                    build_points<int32_t, uint64_t>(P.get(), (const int32_t *)d_coords, (const int32_t *)q_coords,
-                                                    d_offsets, q_offsets, s, hs, sig_keys, sig_slots);
-                else
-                    build_points<int32_t, uint32_t>(P.get(), (const int32_t *)d_coords,
-                                                    (const int32_t *)q_coords, d_offsets, q_offsets, s, hs,
-                                                    sig_keys, sig_slots);
-            }
-            sig_keys.reset();
-            sig_slots.reset();
-            const uint64_t tiles = ceil_div((uint64_t)std::max<int64_t>(P->E, 1), kBlock * 8);
-            P->scan_words = tiles * 4;
-            P->scan_status.alloc(P->scan_words * 8, s);
-            P->scan_ticket.alloc(16, s);
-            if (P->E > 0) {
-                const bool tuned = !(flags & DOM_AGG_NO_TUNE) && tune_lookup(P.get());
-                DevBuf k, v;
-                if (P->key64) build_records<uint64_t>(P.get(), s, &hs, true, k, v);
-                else build_records<uint32_t>(P.get(), s, &hs, true, k, v);
-                P->rkeys = std::move(k);
-                P->rvals = std::move(v);
-                if (!(flags & DOM_AGG_NO_TUNE) && !tuned) tune_plan(P.get(), s);
-                if (flags & DOM_AGG_RECOMPUTE) {
-                    P->rkeys.reset();
-                    P->rvals.reset();
-                } else {
-                    // the last-axis-ordered state is only needed to rebuild the records
-                    P->rs.reset();
-                    P->pay.reset();
-                    P->inst_s.reset();
-                    P->off.reset();
-                }
-            }
-            HIPCHK(hipStreamSynchronize(s));
-        }
+        auto P = make_plan(m, coord_dtype, d_coords, q_coords, n_inst, d_offsets, q_offsets, flags,
+                           static_cast<hipStream_t>(stream), nullptr, DOM_AGG_F32, false);
         *plan = P.release();
+    });
+}
+
+dom_agg_status dom_agg_run(int m, dom_agg_dtype coord_dtype, const void *d_coords, const void *q_coords,
+                           int64_t n_inst, const int64_t *d_offsets, const int64_t *q_offsets, dom_agg_op op,
+                           dom_agg_dtype weight_dtype, const void *weights, void *out, uint32_t flags,
+                           void *stream) {
+    return guarded([&] {
+        check_plan_args(m, coord_dtype, d_coords, q_coords, n_inst, d_offsets, q_offsets);
+        if (flags & ~(uint32_t)DOM_AGG_NO_TUNE) fail(DOM_AGG_EINVAL, "unknown flags 0x%x", flags);
+        const int64_t nD = d_offsets[n_inst], nQ = q_offsets[n_inst];
+        check_forward_args(op, weight_dtype, weights, out, nD, nQ);
+        if (nQ == 0) return;
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        // 4-byte weights (and no weights) travel inside the records
+        const bool inl = op == DOM_AGG_COUNT || weight_dtype == DOM_AGG_I32 || weight_dtype == DOM_AGG_F32;
+        auto P = make_plan(m, coord_dtype, d_coords, q_coords, n_inst, d_offsets, q_offsets, flags, s,
+                           op == DOM_AGG_COUNT ? nullptr : weights, weight_dtype, inl);
+        ensure_part(P.get(), value_bytes(op, weight_dtype), s);
+        const void *kp = P->rkeys.p;
+        const uint32_t *vp = P->rvals.as<uint32_t>();
+        if (P->key64) forward_dispatch<uint64_t>(P.get(), op, weight_dtype, kp, vp, weights, out, s);
+        else forward_dispatch<uint32_t>(P.get(), op, weight_dtype, kp, vp, weights, out, s);
+        // the plan's buffers go back stream-ordered (or through hipFree, which waits)
     });
 }
 
@@ -1235,20 +1368,13 @@ dom_agg_status dom_agg_forward(dom_agg_plan_t plan, dom_agg_op op, dom_agg_dtype
                                const void *weights, void *out, void *stream) {
     return guarded([&] {
         if (!plan) fail(DOM_AGG_EINVAL, "plan is NULL");
-        if (op != DOM_AGG_SUM && op != DOM_AGG_MAX && op != DOM_AGG_COUNT)
-            fail(DOM_AGG_EINVAL, "unknown op %d", (int)op);
-        if (op != DOM_AGG_COUNT && (weight_dtype < DOM_AGG_I32 || weight_dtype > DOM_AGG_F64))
-            fail(DOM_AGG_EINVAL, "unknown weight dtype %d", (int)weight_dtype);
-        if (op != DOM_AGG_COUNT && plan->nD > 0 && !weights) fail(DOM_AGG_EINVAL, "weights are NULL");
-        if (plan->nQ > 0 && !out) fail(DOM_AGG_EINVAL, "out is NULL");
+        check_forward_args(op, weight_dtype, weights, out, plan->nD, plan->nQ);
         if (plan->nQ == 0) return;
         int dev;
         require_gfx950(&dev);
         if (dev != plan->device) fail(DOM_AGG_EINVAL, "plan belongs to device %d, current is %d", plan->device, dev);
         hipStream_t s = static_cast<hipStream_t>(stream);
-        const bool wide = op == DOM_AGG_COUNT || (op == DOM_AGG_SUM && weight_dtype != DOM_AGG_F32) ||
-                          weight_dtype == DOM_AGG_I64 || weight_dtype == DOM_AGG_F64;
-        ensure_part(plan, wide ? 8 : 4, s);
+        ensure_part(plan, value_bytes(op, weight_dtype), s);
         const std::vector<uintptr_t> key{1, (uintptr_t)op, (uintptr_t)weight_dtype, (uintptr_t)weights,
                                          (uintptr_t)out};
         maybe_graph(plan, key, s, [&](hipStream_t cs) {

@@ -131,6 +131,8 @@ struct RankProblem {
     const uint32_t *slots;
     uint32_t *rank;
     uint32_t *kcount;  // [n_inst]
+    uint32_t n;        // points: slots read from the sorted list are checked against it
+    uint32_t n_inst;
     // POS only
     uint32_t nQ;
     const int64_t *doff, *qoff;  // instance offsets of data and queries, or null (one instance)
@@ -153,6 +155,7 @@ struct RankProblem {
     __device__ void emit(uint64_t i, const Raw &cur, V, V, V incl, bool last) const {
         const uint32_t r = (uint32_t)incl - 1u;
         const uint32_t ins = inst(cur);
+        if (cur.slot >= n || ins >= n_inst) return;  // only if the sort were wrong
         if constexpr (POS) {
             // data points up to and including element i, in this instance
             const uint64_t cd = incl >> 32;
@@ -160,12 +163,14 @@ struct RankProblem {
             uint32_t sp;
             if (cur.slot >= nQ) {
                 const uint32_t p = (uint32_t)(dbase + cd - 1u);
+                if (p >= n - nQ) return;
                 dinv[p] = cur.slot - nQ;
                 sp = nQ + p;
             } else {
                 // element i is the (i - dbase - qbase)-th of its instance,
                 // cd of those before it are data
                 const uint32_t p = (uint32_t)(i - dbase - cd);
+                if (p >= nQ) return;
                 qinv[p] = cur.slot;
                 sp = p;
             }
@@ -186,6 +191,22 @@ __global__ void gather_kernel(const T *__restrict__ src, const uint32_t *__restr
     for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) dst[p] = src[idx[p]];
 }
 
+// Records that carry their weights: rw[s] = rank of the first axis (low
+// half) | bits of the weight of data point s - nQ, taken from input row
+// dinv[s - nQ] (high half; 0 for queries or without weights).  W: a 4-byte
+// weight type.
+template <class W>
+__global__ void pack_rank_weight_kernel(const uint32_t *__restrict__ rank0, const uint32_t *__restrict__ dinv,
+                                        const W *__restrict__ w, uint32_t nQ, uint64_t n, uint64_t *__restrict__ rw) {
+    static_assert(sizeof(W) == 4, "");
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += stride) {
+        uint32_t wb = 0;
+        if (w && s >= nQ) __builtin_memcpy(&wb, &w[dinv[s - nQ]], 4);
+        rw[s] = (uint64_t)rank0[s] | ((uint64_t)wb << 32);
+    }
+}
+
 // dst[idx[p]] = src[p]: results back into input order.
 template <class T>
 __global__ void scatter_kernel(const T *__restrict__ src, const uint32_t *__restrict__ idx, T *__restrict__ dst,
@@ -201,7 +222,7 @@ __global__ void scatter_kernel(const T *__restrict__ src, const uint32_t *__rest
 // side effect the point's ranks, payload and instance are laid out in that
 // order for the emitter.
 
-template <class K, int NAX>
+template <class K, int NAX, bool INL = false>
 struct CountProblem {
     using V = uint64_t;
     struct Raw {
@@ -217,6 +238,10 @@ struct CountProblem {
     uint32_t *rs;           // [NAX][n] by position
     uint32_t *pay;          // [n] by position: record payload of the point
     uint32_t *inst_s;       // [n] by position, or null
+    // INL: first-axis rank and weight bits packed by slot (rank low, weight
+    // high); wv[i] receives the weight bits of data points
+    const uint64_t *rw;
+    uint32_t *wv;
 
     __device__ static uint32_t inst(const Raw &r) {
         if constexpr (sizeof(K) == 8) return (uint32_t)(r.key >> 32);
@@ -229,10 +254,18 @@ struct CountProblem {
     __device__ V value(const Raw &, bool, const Raw &cur, uint64_t i) const {
         const bool isq = cur.slot < nQ;
         const uint32_t ins = inst(cur);
+        if (cur.slot >= n || ins >= n_inst) return 0ull;  // only if the sort were wrong: no records
         uint64_t c = 1;
 #pragma unroll
         for (int a = 0; a < NAX; ++a) {
-            const uint32_t r = rank[(uint64_t)a * n + cur.slot];
+            uint32_t r;
+            if (INL && a == 0) {
+                const uint64_t x = rw[cur.slot];  // one gather for the rank and the weight
+                r = (uint32_t)x;
+                if (!isq) wv[i] = (uint32_t)(x >> 32);
+            } else {
+                r = rank[(uint64_t)a * n + cur.slot];
+            }
             const uint32_t L = ltab[(uint64_t)a * n_inst + ins];
             const uint32_t pc = (uint32_t)__popc(r);
             c *= isq ? pc : (L - pc);
@@ -296,6 +329,11 @@ struct EmitArgs {
     unsigned long long *cls_status;      // [chunks][kMaxClasses] look-back words
     uint32_t *ticket;
     uint32_t *error;                     // set when a chunk's records disagree with its class counts
+    // records carrying weights (flag_shift >= 0): a data record's payload is
+    // its weight bits wv[k]; a query record's payload is its row and its key
+    // has bit flag_shift set (above every digit the sort looks at)
+    const uint32_t *wv;
+    int flag_shift;
 };
 
 // Sum of the 16-bit fields of `packed` below field q (q <= 4).
@@ -329,6 +367,7 @@ struct PointCache {
     static constexpr int kCap = 512;
     uint32_t off[kCap + 1];  // record offsets relative to the chunk's first point
     uint32_t pay[kCap];
+    uint32_t wv[kCap];
     uint32_t inst[kCap];
     uint32_t rank[NAX > 0 ? NAX : 1][kCap];
 };
@@ -340,12 +379,12 @@ struct PointCache {
 template <int NAX>
 struct PointWalk {
     uint32_t r[3], L[3], full[3], rem[3];
-    uint32_t payload, inst;
+    uint32_t payload, inst;  // payload: what the point's records carry
     bool isq;
 
-    __device__ void set(const EmitArgs &a, uint32_t pay, uint32_t ins, const uint32_t *ranks) {
-        payload = pay;
-        isq = (payload & kQueryFlag) != 0u;
+    __device__ void set(const EmitArgs &a, uint32_t pay, uint32_t wbits, uint32_t ins, const uint32_t *ranks) {
+        isq = (pay & kQueryFlag) != 0u;
+        payload = a.flag_shift < 0 ? pay : (isq ? (pay & ~kQueryFlag) : wbits);
         inst = ins;
 #pragma unroll
         for (int ax = 0; ax < NAX; ++ax) {
@@ -359,20 +398,22 @@ struct PointWalk {
     // point k of the chunk (index idx among its points), from the LDS cache or global memory
     __device__ void load(const EmitArgs &a, const PointCache<NAX> *pc, bool cached, uint32_t klo, uint32_t idx) {
         uint32_t rk[3] = {0, 0, 0};
-        uint32_t pay, ins;
+        uint32_t pay, wb, ins;
         if (cached) {
             pay = pc->pay[idx];
+            wb = pc->wv[idx];
             ins = pc->inst[idx];
 #pragma unroll
             for (int ax = 0; ax < NAX; ++ax) rk[ax] = pc->rank[ax][idx];
         } else {
             const uint32_t k = klo + idx;
             pay = a.pay[k];
+            wb = a.wv ? a.wv[k] : 0u;
             ins = a.inst_s ? a.inst_s[k] : 0u;
 #pragma unroll
             for (int ax = 0; ax < NAX; ++ax) rk[ax] = a.rs[(uint64_t)ax * a.n + k];
         }
-        set(a, pay, ins, rk);
+        set(a, pay, wb, ins, rk);
     }
     // positions the walk at the point's t-th record
     __device__ void seek(uint32_t t) {
@@ -388,8 +429,9 @@ struct PointWalk {
         }
     }
     template <class K>
-    __device__ K key(int inst_shift, bool with_inst, const int *field_shift) const {
+    __device__ K key(int inst_shift, bool with_inst, const int *field_shift, int flag_shift) const {
         K key = with_inst ? ((K)inst << inst_shift) : K(0);
+        if (flag_shift >= 0 && isq) key |= K(1) << flag_shift;
 #pragma unroll
         for (int ax = 0; ax < NAX; ++ax) {
             const uint32_t top = 31u - (uint32_t)__clz(rem[ax]);  // highest remaining digit
@@ -565,6 +607,9 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(EmitArgs a, K *__restrict__
     for (int q = 0; q < kMaxClasses; ++q)
         cls_info |= (uint64_t)((uint32_t)a.cls_row0[q] | ((uint32_t)a.cls_passes[q] << 8)) << (16 * q);
 
+    // the key without the query flag of records that carry weights
+    const K kmask = a.flag_shift >= 0 ? ~(K(1) << a.flag_shift) : ~K(0);
+
     const uint64_t nchunks = (a.E + CHUNK - 1) / CHUNK;
     for (;;) {
         __syncthreads();  // previous chunk done with LDS
@@ -583,6 +628,7 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(EmitArgs a, K *__restrict__
             for (uint32_t i = threadIdx.x; i <= npts; i += BLOCK) s_pc.off[i] = (uint32_t)(a.off[klo + i] - obase);
             for (uint32_t i = threadIdx.x; i < npts; i += BLOCK) {
                 s_pc.pay[i] = a.pay[klo + i];
+                s_pc.wv[i] = a.wv ? a.wv[klo + i] : 0u;
                 s_pc.inst[i] = with_inst ? a.inst_s[klo + i] : 0u;
 #pragma unroll
                 for (int ax = 0; ax < NAX; ++ax) s_pc.rank[ax][i] = a.rs[(uint64_t)ax * a.n + klo + i];
@@ -657,10 +703,10 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(EmitArgs a, K *__restrict__
             const bool valid = r0 + j < o1;
             K key = 0;
             if (valid) {
-                key = pw.template key<K>(a.inst_shift, with_inst, a.field_shift);
+                key = pw.template key<K>(a.inst_shift, with_inst, a.field_shift, a.flag_shift);
                 uint32_t lp = threadIdx.x * ITEMS + j;
                 if constexpr (CLS) {
-                    const int q = key_class(key, a.cls_c0);
+                    const int q = key_class(key & kmask, a.cls_c0);
                     lp = packed_prefix(tot, q) + ((uint32_t)(mine >> (16 * q)) & 0xffffu);
                     mine += 1ull << (16 * q);
                     seen += 1ull << (16 * q);
@@ -684,7 +730,7 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(EmitArgs a, K *__restrict__
             if constexpr (!CLS) {
                 hist_add(s_hist, key, valid, a.passes, peel_from);
             } else {
-                const int q = valid ? key_class(key, a.cls_c0) : 0;
+                const int q = valid ? key_class(key & kmask, a.cls_c0) : 0;
                 const uint32_t ci = (uint32_t)(cls_info >> (16 * q));
                 hist_add_rows(s_hist, key, valid, (int)(ci & 0xffu), (int)((ci >> 8) & 0xffu), a.passes);
             }
@@ -705,22 +751,36 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(EmitArgs a, K *__restrict__
                 uint64_t excl = 0;
                 bool done = !act || c == 0;
                 int64_t hi = (int64_t)c - 1;
+                constexpr int kDepth = 4;  // chunks per lane and round trip (loads issued together)
                 while (__ballot(!done)) {
-                    const int64_t t = hi - k;
-                    unsigned long long w = 0;
-                    if (!done && t >= 0) {
-                        while (DW::flag(w = load_agent(&st[(uint64_t)t * kMaxClasses + q])) == 0)
+                    unsigned long long w[kDepth];
+#pragma unroll
+                    for (int d = 0; d < kDepth; ++d) {
+                        const int64_t t = hi - k - 16 * d;
+                        w[d] = (!done && t >= 0) ? load_agent(&st[(uint64_t)t * kMaxClasses + q]) : DW::make(1, 0);
+                    }
+#pragma unroll
+                    for (int d = 0; d < kDepth; ++d) {
+                        const int64_t t = hi - k - 16 * d;
+                        while (DW::flag(w[d]) == 0) {
                             __builtin_amdgcn_s_sleep(2);
+                            w[d] = load_agent(&st[(uint64_t)t * kMaxClasses + q]);
+                        }
                     }
-                    const uint64_t im = __ballot(!done && t >= 0 && DW::flag(w) == kFlagInclusive);
-                    const uint32_t gm = (uint32_t)(im >> (16 * q)) & 0xffffu;
-                    const int k0 = gm ? __ffs(gm) - 1 : 15;  // nearest inclusive chunk of the class
-                    const uint64_t v = row_sum_u64((!done && t >= 0 && k <= k0) ? (uint64_t)(w & DW::kMask) : 0ull);
-                    if (!done) {
-                        excl += v;
-                        done = gm != 0;
-                        hi -= 16;
+#pragma unroll
+                    for (int d = 0; d < kDepth; ++d) {
+                        const int64_t t = hi - k - 16 * d;
+                        const uint64_t im = __ballot(!done && t >= 0 && DW::flag(w[d]) == kFlagInclusive);
+                        const uint32_t gm = (uint32_t)(im >> (16 * q)) & 0xffffu;
+                        const int k0 = gm ? __ffs(gm) - 1 : 15;  // nearest inclusive chunk of the class
+                        const uint64_t v =
+                            row_sum_u64((!done && t >= 0 && k <= k0) ? (uint64_t)(w[d] & DW::kMask) : 0ull);
+                        if (!done) {
+                            excl += v;
+                            done = gm != 0;
+                        }
                     }
+                    hi -= 16 * kDepth;
                 }
                 if (act && k == 0) {
                     if (c > 0) store_agent(&st[c * kMaxClasses + q], DW::make(kFlagInclusive, excl + count));
@@ -818,7 +878,11 @@ struct Monoid {
 // goes to part[slot * nQ + query] (slot mode) or is F-combined atomically
 // into out[query] (atomic mode, for very sparse slot tables).  Payloads and
 // w use the internal numbering of the points.
-template <class K, class W, class Acc, int OP>
+//
+// INL: the records carry the weights (a data record's payload is its weight
+// bits, a query record's key has bit flag_shift set and its payload is the
+// query's row), so the scan reads them in sequence instead of gathering.
+template <class K, class W, class Acc, int OP, bool INL = false>
 struct ForwardProblem {
     using V = Acc;
     struct Raw {
@@ -827,24 +891,42 @@ struct ForwardProblem {
     };
     const K *keys;
     const uint32_t *vals;
-    const W *w;  // unused for COUNT
+    const W *w;  // unused for COUNT and INL
     V *out;      // atomic mode target
     V *part;     // slot mode target, or null
     uint64_t stride;
+    uint64_t nw;     // weights (|D|): payloads are checked against it
     SlotMap sm;
+    int flag_shift;  // INL
 
+    __device__ bool is_query(const Raw &r) const {
+        if constexpr (INL) return ((r.key >> flag_shift) & K(1)) != K(0);
+        else return (r.payload & kQueryFlag) != 0u;
+    }
     __device__ V identity() const { return Monoid<V, OP>::identity(); }
     __device__ V combine(V a, V b) const { return Monoid<V, OP>::combine(a, b); }
     __device__ Raw load(uint64_t i) const { return Raw{keys[i], vals[i]}; }
-    __device__ bool head(const Raw &prev, const Raw &cur) const { return prev.key != cur.key; }
+    __device__ bool head(const Raw &prev, const Raw &cur) const {
+        if constexpr (INL) return ((prev.key ^ cur.key) & ~(K(1) << flag_shift)) != K(0);
+        else return prev.key != cur.key;
+    }
     __device__ V value(const Raw &, bool, const Raw &cur, uint64_t) const {
-        if (cur.payload & kQueryFlag) return identity();
-        if constexpr (OP == OP_COUNT) return V(1);
-        else return V(w[cur.payload]);
+        if (is_query(cur)) return identity();
+        if constexpr (OP == OP_COUNT) {
+            return V(1);
+        } else if constexpr (INL) {
+            static_assert(sizeof(W) == 4, "");
+            W x;
+            __builtin_memcpy(&x, &cur.payload, 4);
+            return V(x);
+        } else {
+            return cur.payload < nw ? V(w[cur.payload]) : identity();  // (always below |D|)
+        }
     }
     __device__ void emit(uint64_t, const Raw &cur, V, V, V incl, bool) const {
-        if (!(cur.payload & kQueryFlag)) return;
-        const uint32_t q = cur.payload & ~kQueryFlag;
+        if (!is_query(cur)) return;
+        const uint32_t q = INL ? cur.payload : (cur.payload & ~kQueryFlag);
+        if (q >= stride) return;  // (rows are < stride = |Q| by construction)
         if (part) {
             const uint32_t sl = sm.slot(cur.key);
             if (sl < sm.n_slots) part[(uint64_t)sl * stride + q] = incl;
@@ -875,6 +957,7 @@ struct BackwardProblem {
     G *grad;
     G *part;
     uint64_t stride;
+    uint64_t ng;  // |Q|
     SlotMap sm;
     uint64_t E;
 
@@ -886,10 +969,13 @@ struct BackwardProblem {
     }
     __device__ bool head(const Raw &prev, const Raw &cur) const { return prev.key != cur.key; }
     __device__ G value(const Raw &, bool, const Raw &cur, uint64_t) const {
-        return (cur.payload & kQueryFlag) ? g[cur.payload & ~kQueryFlag] : G(0);
+        if (!(cur.payload & kQueryFlag)) return G(0);
+        const uint32_t q = cur.payload & ~kQueryFlag;
+        return q < ng ? g[q] : G(0);  // (always below |Q|)
     }
     __device__ void emit(uint64_t, const Raw &cur, G, G excl, G, bool) const {
         if (cur.payload & kQueryFlag) return;
+        if (cur.payload >= stride) return;  // (rows are < stride = |D| by construction)
         if (part) {
             const uint32_t sl = sm.slot(cur.key);
             if (sl < sm.n_slots) part[(uint64_t)sl * stride + cur.payload] = excl;

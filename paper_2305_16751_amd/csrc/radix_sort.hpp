@@ -217,14 +217,28 @@ __global__ __launch_bounds__(BLOCK) void onesweep_kernel(
         s_dstart[tid] = dstart;
         uint32_t excl = 0;
         if (tile > 0) {
-            uint32_t t = tile - 1;
-            for (;;) {
-                S w;
-                while (W::flag(w = load_agent(&status[(uint64_t)t * kRadix + tid])) == 0)
-                    __builtin_amdgcn_s_sleep(2);
-                excl += W::count(w);
-                if (W::flag(w) == kFlagInclusive) break;
-                --t;
+            // Walk back over earlier tiles, four words per round trip (the
+            // loads are issued together; a word not yet published is polled
+            // on its own), until an inclusive word; tile 0's always is.
+            constexpr int kDepth = 4;
+            int64_t t = (int64_t)tile - 1;
+            bool done = false;
+            while (!done) {
+                S w[kDepth];
+#pragma unroll
+                for (int k = 0; k < kDepth; ++k)
+                    w[k] = (t - k >= 0) ? load_agent(&status[(uint64_t)(t - k) * kRadix + tid]) : S(0);
+#pragma unroll
+                for (int k = 0; k < kDepth; ++k) {
+                    if (done || t - k < 0) continue;
+                    while (W::flag(w[k]) == 0) {
+                        __builtin_amdgcn_s_sleep(2);
+                        w[k] = load_agent(&status[(uint64_t)(t - k) * kRadix + tid]);
+                    }
+                    excl += W::count(w[k]);
+                    done = W::flag(w[k]) == kFlagInclusive;
+                }
+                t -= kDepth;
             }
             store_agent(&status[(uint64_t)tile * kRadix + tid], W::make(kFlagInclusive, excl + count));
         }

@@ -41,8 +41,8 @@ __global__ __launch_bounds__(BLOCK) void seg_scan_kernel(P p, uint64_t n,
 
     __shared__ Raw s_raw[TILE + TILE / ITEMS];
     __shared__ Raw s_pred, s_succ;
-    __shared__ V s_wval[WAVES], s_wpre[WAVES];
-    __shared__ uint32_t s_wflag[WAVES], s_wpref[WAVES];
+    __shared__ V s_wval[WAVES];
+    __shared__ uint32_t s_wflag[WAVES];
     __shared__ V s_carry;
     __shared__ uint32_t s_tile;
 
@@ -117,16 +117,37 @@ __global__ __launch_bounds__(BLOCK) void seg_scan_kernel(P p, uint64_t n,
     }
     __syncthreads();
 
+    // This wavefront's prefix within the tile: the combined totals of the
+    // wavefronts before it, and whether a segment starts among them.
+    V wpre = p.identity();
+    uint32_t wpref = 0;
+    for (int w = 0; w < wave; ++w) {
+        wpre = s_wflag[w] ? s_wval[w] : p.combine(wpre, s_wval[w]);
+        wpref |= s_wflag[w];
+    }
+    // The thread's items depend on the tile's carry-in only if no segment
+    // starts in the tile before them; all other threads emit at once, while
+    // wavefront 0 is still looking back.
+    const bool needs_carry = !(wpref || ex_f);
+    auto emit_items = [&](V run) {
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint64_t i = base + l0 + j;
+            if (i < n) {
+                if ((heads >> j) & 1u) run = p.identity();
+                const V excl = run;
+                run = p.combine(run, v[j]);
+                p.emit(i, s_raw[pidx(l0 + j)], v[j], excl, run, (heads >> (j + 1)) & 1u);
+            }
+        }
+    };
+
     // Wavefront 0 combines the wavefront totals, publishes the tile's status
     // and looks back.  Every lane computes the same values; lane 0 writes.
     if (wave == 0) {
         V run = p.identity();
         uint32_t rf = 0;
         for (int w = 0; w < WAVES; ++w) {
-            if (lane == 0) {
-                s_wpre[w] = run;
-                s_wpref[w] = rf;
-            }
             run = s_wflag[w] ? s_wval[w] : p.combine(run, s_wval[w]);
             rf |= s_wflag[w];
         }
@@ -139,55 +160,85 @@ __global__ __launch_bounds__(BLOCK) void seg_scan_kernel(P p, uint64_t n,
         }
         V carry = p.identity();
         if (!first_is_head) {
-            // Find the nearest earlier tile with an inclusive value, 64 tiles
-            // per round trip (lane l reads tile hi - l), then fold the
-            // aggregates of the tiles after it left to right, 64 per round
-            // trip.  Every inclusive value is therefore the same left fold
+            // Find the nearest earlier tile with an inclusive value, then fold
+            // the aggregates of the tiles after it left to right.  Each lane
+            // reads kDepth tiles per round trip (lane l, slot k: distance
+            // 64 k + l), their loads issued together, so a round trip covers
+            // 64 kDepth tiles.  Every inclusive value is the same left fold
             // from its segment's start whatever the timing, so floating-point
             // results do not depend on scheduling.
+            constexpr int kDepth = 4;
             int64_t hi = (int64_t)tile - 1, t0 = -1;
             V incl_v = p.identity();
             for (;;) {
-                const int64_t t = hi - lane;
-                V pv = p.identity();
-                uint32_t fl = 0;
-                if (t >= 0) fl = wait_status<V>(status, (uint32_t)t, pv);
-                const uint64_t im = __ballot(fl == kFlagInclusive);
-                if (im) {
-                    const int l = __ffsll((unsigned long long)im) - 1;  // nearest
-                    t0 = hi - l;
-                    incl_v = read_lane(pv, l);
-                    break;
+                V pv[kDepth];
+                uint32_t fl[kDepth];
+#pragma unroll
+                for (int k = 0; k < kDepth; ++k) {
+                    const int64_t t = hi - lane - kWave * k;
+                    pv[k] = p.identity();
+                    fl[k] = t >= 0 ? try_status<V>(status, (uint32_t)t, pv[k]) : kFlagAggregate;
                 }
-                hi -= kWave;
+                // Only the published run of tiles nearest to this one
+                // matters: stop at its first inclusive value, and poll again
+                // only while that run is cut short by an unpublished tile.
+                bool found = false;
+#pragma unroll
+                for (int k = 0; k < kDepth; ++k) {
+                    if (found) continue;
+                    const int64_t t = hi - lane - kWave * k;
+                    for (;;) {
+                        const uint64_t pub = __ballot(fl[k] != 0);
+                        const uint64_t inc = __ballot(t >= 0 && fl[k] == kFlagInclusive);
+                        const int run = pub == ~0ull ? kWave : __ffsll((unsigned long long)~pub) - 1;
+                        const uint64_t near = inc & (run == kWave ? ~0ull : ((1ull << run) - 1ull));
+                        if (near) {
+                            const int l = __ffsll((unsigned long long)near) - 1;  // nearest
+                            t0 = hi - l - kWave * k;
+                            incl_v = read_uniform_lane(pv[k], l);
+                            found = true;
+                            break;
+                        }
+                        if (run == kWave) break;  // 64 aggregates: on to the next slot
+                        __builtin_amdgcn_s_sleep(1);
+                        if (fl[k] == 0) fl[k] = try_status<V>(status, (uint32_t)t, pv[k]);
+                    }
+                }
+                if (found) break;
+                hi -= kWave * kDepth;
             }
             carry = incl_v;
-            for (int64_t w0 = t0 + 1; w0 < (int64_t)tile; w0 += kWave) {
-                const int64_t t = w0 + lane;
-                V av = p.identity();
-                if (t < (int64_t)tile) (void)wait_status<V>(aggs, (uint32_t)t, av);
-                const int cnt = (int)(((int64_t)tile - w0) < kWave ? ((int64_t)tile - w0) : kWave);
-                for (int k = 0; k < cnt; ++k) carry = p.combine(carry, read_lane(av, k));
+            for (int64_t w0 = t0 + 1; w0 < (int64_t)tile; w0 += kWave * kDepth) {
+                V av[kDepth];
+                uint32_t fl[kDepth];
+#pragma unroll
+                for (int k = 0; k < kDepth; ++k) {
+                    const int64_t t = w0 + kWave * k + lane;
+                    av[k] = p.identity();
+                    fl[k] = t < (int64_t)tile ? try_status<V>(aggs, (uint32_t)t, av[k]) : kFlagAggregate;
+                }
+#pragma unroll
+                for (int k = 0; k < kDepth; ++k) {
+                    const int64_t t = w0 + kWave * k + lane;
+                    while (fl[k] == 0) {
+                        __builtin_amdgcn_s_sleep(1);
+                        fl[k] = try_status<V>(aggs, (uint32_t)t, av[k]);
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < kDepth; ++k) {
+                    const int64_t left = (int64_t)tile - (w0 + kWave * k);
+                    const int cnt = left <= 0 ? 0 : (left < kWave ? (int)left : kWave);
+                    for (int l = 0; l < cnt; ++l) carry = p.combine(carry, read_uniform_lane(av[k], l));
+                }
             }
             if (!rf && lane == 0) publish_status(status, tile, kFlagInclusive, p.combine(carry, run));
         }
         if (lane == 0) s_carry = carry;
     }
+    if (!needs_carry) emit_items(ex_f ? ex_v : p.combine(wpre, ex_v));
     __syncthreads();
-
-    V run = s_carry;
-    run = s_wpref[wave] ? s_wpre[wave] : p.combine(run, s_wpre[wave]);
-    run = ex_f ? ex_v : p.combine(run, ex_v);
-#pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-        const uint64_t i = base + l0 + j;
-        if (i < n) {
-            if ((heads >> j) & 1u) run = p.identity();
-            const V excl = run;
-            run = p.combine(run, v[j]);
-            p.emit(i, s_raw[pidx(l0 + j)], v[j], excl, run, (heads >> (j + 1)) & 1u);
-        }
-    }
+    if (needs_carry) emit_items(p.combine(p.combine(s_carry, wpre), ex_v));
 }
 
 }  // namespace domagg

@@ -18,12 +18,12 @@
 namespace domagg {
 
 struct TuneChoice {
-    int record_sort_tile = 4096;  // onesweep tile: 2048 (256 x 8), 4096 (256 x 16) or 8192 (512 x 16)
+    int record_sort_tile = 4096;  // onesweep tile: 2048 (256 x 8), 4096 (256 x 16), 8192 (512 x 16) or 16384 (512 x 32)
     int point_sort_tile = 4096;
     int scan_items = 16;          // segmented-scan tile = 256 * items (8 forced for 64-bit keys)
 };
 
-inline bool valid_sort_tile(int t) { return t == 2048 || t == 4096 || t == 8192; }
+inline bool valid_sort_tile(int t) { return t == 2048 || t == 4096 || t == 8192 || t == 16384; }
 
 inline TuneChoice default_tune() { return TuneChoice{}; }
 

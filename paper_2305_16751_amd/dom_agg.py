@@ -6,6 +6,7 @@ everything else is the HIP library.
 
     out = dom_agg(d, q, w, op="sum")            # autograd on w for op="sum"
     out = dom_agg_batched(d, q, w, d_off, q_off, op="sum")
+    out = dom_agg_run(d, q, w, op="sum")        # one-shot forward (no plan kept)
     plan = DomAggPlan(d, q)                     # coordinate-only phase, reusable
     out = plan.forward(w, "max"); gw = plan.backward(grad_out)
 """
@@ -79,6 +80,39 @@ def _coords(x: torch.Tensor, name: str) -> torch.Tensor:
     return x.contiguous()
 
 
+def _offsets(nD: int, nQ: int, d_offsets, q_offsets):
+    if d_offsets is None and q_offsets is None:
+        return np.array([0, nD], dtype=np.int64), np.array([0, nQ], dtype=np.int64)
+    doff = np.ascontiguousarray(np.asarray(d_offsets, dtype=np.int64))
+    qoff = np.ascontiguousarray(np.asarray(q_offsets, dtype=np.int64))
+    if doff.shape != qoff.shape or doff.ndim != 1 or doff.size < 2:
+        raise ValueError("offsets must be 1-D arrays of equal length n_inst + 1")
+    if doff[-1] != nD or qoff[-1] != nQ:
+        raise ValueError("offsets must end at the number of rows")
+    return doff, qoff
+
+
+def _weights(w, op: str, nD: int, device):
+    if op not in B.OPS:
+        raise ValueError(f"op must be one of {list(B.OPS)}")
+    if op == "count":
+        return None, None
+    if w is None or w.device != device or w.shape != (nD,):
+        raise ValueError(f"w must be a [{nD}] tensor on {device}")
+    if w.dtype not in _TORCH_TO_DT:
+        raise ValueError(f"unsupported weight dtype {w.dtype}")
+    return w.contiguous(), w.dtype
+
+
+def _out(out, op: str, wdt, nQ: int, device):
+    odt = _out_dtype(op, wdt)
+    if out is None:
+        return torch.empty(nQ, dtype=odt, device=device)
+    if out.dtype != odt or out.shape != (nQ,) or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous [{nQ}] {odt} tensor")
+    return out
+
+
 class DomAggPlan:
     """The coordinate-only phase: ranks, flat map and the sorted records.
 
@@ -99,16 +133,7 @@ class DomAggPlan:
         self.m = int(d.shape[1])
         self.nD, self.nQ = int(d.shape[0]), int(q.shape[0])
         self.device = d.device
-        if d_offsets is None and q_offsets is None:
-            doff = np.array([0, self.nD], dtype=np.int64)
-            qoff = np.array([0, self.nQ], dtype=np.int64)
-        else:
-            doff = np.ascontiguousarray(np.asarray(d_offsets, dtype=np.int64))
-            qoff = np.ascontiguousarray(np.asarray(q_offsets, dtype=np.int64))
-            if doff.shape != qoff.shape or doff.ndim != 1 or doff.size < 2:
-                raise ValueError("offsets must be 1-D arrays of equal length n_inst + 1")
-            if doff[-1] != self.nD or qoff[-1] != self.nQ:
-                raise ValueError("offsets must end at the number of rows")
+        doff, qoff = _offsets(self.nD, self.nQ, d_offsets, q_offsets)
         self.n_inst = int(doff.size - 1)
         flags = (B.RECOMPUTE if recompute else 0) | (B.GRAPH if graph else 0) | (0 if tune else B.NO_TUNE)
         h = ctypes.c_void_p()
@@ -125,22 +150,8 @@ class DomAggPlan:
         return inf.as_dict()
 
     def forward(self, w: torch.Tensor | None = None, op: str = "sum", out: torch.Tensor | None = None):
-        if op not in B.OPS:
-            raise ValueError(f"op must be one of {list(B.OPS)}")
-        if op == "count":
-            wdt = None
-        else:
-            if w is None or w.device != self.device or w.shape != (self.nD,):
-                raise ValueError(f"w must be a [{self.nD}] tensor on {self.device}")
-            if w.dtype not in _TORCH_TO_DT:
-                raise ValueError(f"unsupported weight dtype {w.dtype}")
-            w = w.contiguous()
-            wdt = w.dtype
-        odt = _out_dtype(op, wdt)
-        if out is None:
-            out = torch.empty(self.nQ, dtype=odt, device=self.device)
-        elif out.dtype != odt or out.shape != (self.nQ,) or not out.is_contiguous():
-            raise ValueError(f"out must be a contiguous [{self.nQ}] {odt} tensor")
+        w, wdt = _weights(w, op, self.nD, self.device)
+        out = _out(out, op, wdt, self.nQ, self.device)
         with torch.cuda.device(self.device):
             B.check(self._lib.dom_agg_forward(self._h, B.OPS[op], _TORCH_TO_DT.get(wdt, B.I64),
                                               _ptr(w) if op != "count" else None, _ptr(out), _stream()))
@@ -182,20 +193,49 @@ class DomAggFunction(torch.autograd.Function):
         return ctx.plan.backward(grad_out.to(ctx.wdtype)), None
 
 
+def dom_agg_run(d: torch.Tensor, q: torch.Tensor, w: torch.Tensor | None = None, op: str = "sum",
+                d_offsets=None, q_offsets=None, out: torch.Tensor | None = None, tune: bool = True):
+    """One-shot forward (no plan is kept; the records carry the weights)."""
+    lib = _lib()
+    d = _coords(d, "d")
+    q = _coords(q, "q")
+    if d.shape[1] != q.shape[1] or d.dtype != q.dtype:
+        raise ValueError("d and q must have the same dtype and dimension")
+    nD, nQ = int(d.shape[0]), int(q.shape[0])
+    doff, qoff = _offsets(nD, nQ, d_offsets, q_offsets)
+    w, wdt = _weights(w, op, nD, d.device)
+    out = _out(out, op, wdt, nQ, d.device)
+    with torch.cuda.device(d.device):
+        B.check(lib.dom_agg_run(int(d.shape[1]), _TORCH_TO_DT[d.dtype], _ptr(d), _ptr(q), int(doff.size - 1),
+                                doff.ctypes.data_as(ctypes.c_void_p), qoff.ctypes.data_as(ctypes.c_void_p),
+                                B.OPS[op], _TORCH_TO_DT.get(wdt, B.I64), _ptr(w) if op != "count" else None,
+                                _ptr(out), 0 if tune else B.NO_TUNE, _stream()))
+    return out
+
+
+def _needs_grad(w, op):
+    return op == "sum" and w is not None and w.requires_grad and w.dtype in (torch.float32, torch.float64)
+
+
 def dom_agg(d: torch.Tensor, q: torch.Tensor, w: torch.Tensor | None = None, op: str = "sum",
             **plan_kwargs) -> torch.Tensor:
     """For every query row of q: F over w[i] of the data rows d[i] strictly
     below it in every coordinate (e when none).  Differentiable in w for
-    op="sum" with float weights."""
+    op="sum" with float weights (a plan is then kept for the backward);
+    otherwise one one-shot call."""
+    if not _needs_grad(w, op) and not plan_kwargs:
+        return dom_agg_run(d, q, w, op)
     plan = DomAggPlan(d, q, **plan_kwargs)
-    if op == "sum" and w is not None and w.requires_grad and w.dtype in (torch.float32, torch.float64):
+    if _needs_grad(w, op):
         return DomAggFunction.apply(w, plan)
     return plan.forward(w, op)
 
 
 def dom_agg_batched(d, q, w, d_offsets, q_offsets, op: str = "sum", **plan_kwargs) -> torch.Tensor:
     """dom_agg over independent instances stacked along the rows."""
+    if not _needs_grad(w, op) and not plan_kwargs:
+        return dom_agg_run(d, q, w, op, d_offsets, q_offsets)
     plan = DomAggPlan(d, q, d_offsets, q_offsets, **plan_kwargs)
-    if op == "sum" and w is not None and w.requires_grad and w.dtype in (torch.float32, torch.float64):
+    if _needs_grad(w, op):
         return DomAggFunction.apply(w, plan)
     return plan.forward(w, op)

@@ -98,6 +98,38 @@ def test_allocator_hook_pairs(B):
     assert lib.dom_agg_set_allocator(ctypes.cast(None, B.ALLOC_FN), ctypes.cast(None, B.RELEASE_FN), None) == B.OK
 
 
+def _run(B, m=2, dt=None, d=1, q=1, n_inst=1, doff=None, qoff=None, op=0, wdt=None, w=1, out=1, flags=0):
+    lib = B.load()
+    dt = B.F32 if dt is None else dt
+    wdt = B.F32 if wdt is None else wdt
+    doff = np.array([0, 4] if doff is None else doff, dtype=np.int64)
+    qoff = np.array([0, 3] if qoff is None else qoff, dtype=np.int64)
+    p = lambda x: ctypes.c_void_p(x) if x else None  # noqa: E731
+    return lib.dom_agg_run(m, dt, p(d), p(q), n_inst, doff.ctypes.data_as(ctypes.c_void_p),
+                           qoff.ctypes.data_as(ctypes.c_void_p), op, wdt, p(w), p(out), flags, None)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(m=0), "EINVAL"), (dict(dt=3), "EUNSUPPORTED"), (dict(n_inst=0), "EINVAL"),
+    (dict(doff=[1, 4]), "EINVAL"), (dict(d=0), "EINVAL"), (dict(flags=2), "EINVAL"), (dict(flags=4), "EINVAL"),
+    (dict(op=7), "EINVAL"), (dict(wdt=9), "EINVAL"), (dict(w=0), "EINVAL"), (dict(out=0), "EINVAL"),
+    (dict(doff=[0, 1 << 30], qoff=[0, 1 << 30]), "ETOOBIG"),
+])
+def test_run_argument_validation(B, kw, status):
+    st = _run(B, **kw)
+    assert B.STATUS_NAMES[st] == status
+    assert B.load().dom_agg_last_error()
+
+
+def test_run_count_needs_no_weights_and_reports_enodev_without_device(B):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    assert B.STATUS_NAMES[_run(B, op=B.COUNT, w=0)] == "ENODEV"
+    # nothing to write: accepted without touching a device
+    assert _run(B, qoff=[0, 0], out=0) == B.OK
+
+
 def test_valid_plan_without_device_reports_enodev(B):
     import torch
     if torch.cuda.is_available():

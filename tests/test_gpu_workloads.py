@@ -197,3 +197,21 @@ def test_batched_gmm4d():
         p = DomAggPlan(to_dev(D), to_dev(Q))
         check_exact(p.forward(to_dev(wik), "max"), mx[qoff[k]:qoff[k + 1]], f"max per-instance {k}")
         p.close()
+
+
+def test_f32_2d_16m_one_shot():
+    """The one-shot entry point at the full size: every count exact (Fenwick
+    sweep), sampled sums against the fp64 definition."""
+    from paper_2305_16751_amd import dom_agg_run
+    c = workloads.f32_2d_16m()
+    print(f"f32_2d_16m one-shot |D|={c.D.shape[0]} |Q|={c.Q.shape[0]}", flush=True)
+    d, q = to_dev(c.D), to_dev(c.Q)
+    out = dom_agg_run(d, q, to_dev(c.w), "sum").cpu().numpy()
+    cnt = dom_agg_run(d, q, None, "count").cpu().numpy()
+    del d, q
+    torch.cuda.empty_cache()
+    np.testing.assert_array_equal(cnt, oracle.fenwick2(c.D, c.Q, None, "count"))
+    idx = _sample(c.Q.shape[0], 96, 12)
+    w64 = c.w.astype(np.float64)
+    check_fp(torch.from_numpy(out[idx]), oracle.brute(2, c.D, c.Q[idx], w64, "sum"),
+             oracle.brute(2, c.D, c.Q[idx], np.abs(w64), "sum"), "f32_2d_16m one-shot sum")
