@@ -378,15 +378,15 @@ const char *onesweep_name(int tile) {
     return names[ROLE][sizeof(K) == 8][ti];
 }
 
-template <class K, class S, int BLOCK, int ITEMS, int ROLE>
-void onesweep_launch(const K *kin, const uint32_t *vin, K *kout, uint32_t *vout, uint32_t n,
+template <class K, class S, int BLOCK, int ITEMS, int ROLE, class VT>
+void onesweep_launch(const K *kin, const VT *vin, K *kout, VT *vout, uint32_t n,
                      int shift, const uint32_t *bases, S *status, uint32_t *ticket, hipStream_t s) {
     constexpr int TILE = BLOCK * ITEMS;
     const unsigned tiles = (unsigned)ceil_div(n, TILE);
     clear_lookback(reinterpret_cast<uint64_t *>(status), ceil_div((uint64_t)tiles * kRadix * sizeof(S), 8),
                    ticket, s);
     launch(onesweep_name<K, ROLE>(TILE), s, [&] {
-        onesweep_kernel<K, S, BLOCK, ITEMS, ROLE><<<tiles, BLOCK, 0, s>>>(kin, vin, kout, vout, n, shift,
+        onesweep_kernel<K, S, BLOCK, ITEMS, ROLE, VT><<<tiles, BLOCK, 0, s>>>(kin, vin, kout, vout, n, shift,
                                                                           bases, status, ticket);
     });
 }
@@ -400,27 +400,34 @@ int effective_tile(int tile) {
     return tile;
 }
 
-template <class K, class S, int ROLE>
-void onesweep_dispatch(int tile, const K *kin, const uint32_t *vin, K *kout, uint32_t *vout, uint32_t n,
+template <class K, class S, int ROLE, class VT>
+void onesweep_dispatch(int tile, const K *kin, const VT *vin, K *kout, VT *vout, uint32_t n,
                        int shift, const uint32_t *bases, void *status, uint32_t *ticket, hipStream_t s) {
     S *st = static_cast<S *>(status);
-    if (tile == 2048) onesweep_launch<K, S, 256, 8, ROLE>(kin, vin, kout, vout, n, shift, bases, st, ticket, s);
-    else if (tile == 8192) onesweep_launch<K, S, 512, 16, ROLE>(kin, vin, kout, vout, n, shift, bases, st, ticket, s);
-    else if (tile == 16384) {
+    if constexpr (sizeof(VT) == 8) {
+        // 64-bit payloads: one tile shape
+        onesweep_launch<K, S, 256, 16, ROLE, VT>(kin, vin, kout, vout, n, shift, bases, st, ticket, s);
+    } else if (tile == 2048) {
+        onesweep_launch<K, S, 256, 8, ROLE, VT>(kin, vin, kout, vout, n, shift, bases, st, ticket, s);
+    } else if (tile == 8192) {
+        onesweep_launch<K, S, 512, 16, ROLE, VT>(kin, vin, kout, vout, n, shift, bases, st, ticket, s);
+    } else if (tile == 16384) {
         if constexpr (ROLE == 1 && sizeof(K) == 4)
-            onesweep_launch<K, S, 512, 32, ROLE>(kin, vin, kout, vout, n, shift, bases, st, ticket, s);
+            onesweep_launch<K, S, 512, 32, ROLE, VT>(kin, vin, kout, vout, n, shift, bases, st, ticket, s);
         else
             fail(DOM_AGG_EHIP, "internal: no 16384-element tile for this sort");
-    } else onesweep_launch<K, S, 256, 16, ROLE>(kin, vin, kout, vout, n, shift, bases, st, ticket, s);
+    } else {
+        onesweep_launch<K, S, 256, 16, ROLE, VT>(kin, vin, kout, vout, n, shift, bases, st, ticket, s);
+    }
 }
 
 // Sorts (kA, vA) by the listed digit shifts; returns true when the result
 // ended up in (kB, vB).  bases: [passes][256] (pass p at shift 8p).
-template <class K, int ROLE>
-bool radix_sort(K *kA, uint32_t *vA, K *kB, uint32_t *vB, uint64_t n, const std::vector<int> &shifts,
+template <class K, int ROLE, class VT = uint32_t>
+bool radix_sort(K *kA, VT *vA, K *kB, VT *vB, uint64_t n, const std::vector<int> &shifts,
                 const uint32_t *bases, int tile, hipStream_t s) {
     if (n == 0 || shifts.empty()) return false;
-    tile = effective_tile<K, ROLE>(tile);
+    tile = sizeof(VT) == 8 ? 4096 : effective_tile<K, ROLE>(tile);
     const bool narrow = n < (1ull << 30);  // every digit count fits 30 bits
     DevBuf status, ticket;
     status.alloc(ceil_div(n, tile) * kRadix * (narrow ? 4 : 8) + 8, s);
@@ -428,15 +435,15 @@ bool radix_sort(K *kA, uint32_t *vA, K *kB, uint32_t *vB, uint64_t n, const std:
     bool inB = false;
     for (int sh : shifts) {
         const K *ki = inB ? kB : kA;
-        const uint32_t *vi = inB ? vB : vA;
+        const VT *vi = inB ? vB : vA;
         K *ko = inB ? kA : kB;
-        uint32_t *vo = inB ? vA : vB;
+        VT *vo = inB ? vA : vB;
         const uint32_t *b = bases + (sh / kRadixBits) * kRadix;
         if (narrow)
-            onesweep_dispatch<K, uint32_t, ROLE>(tile, ki, vi, ko, vo, (uint32_t)n, sh, b, status.p,
+            onesweep_dispatch<K, uint32_t, ROLE, VT>(tile, ki, vi, ko, vo, (uint32_t)n, sh, b, status.p,
                                                  ticket.as<uint32_t>(), s);
         else
-            onesweep_dispatch<K, uint64_t, ROLE>(tile, ki, vi, ko, vo, (uint32_t)n, sh, b, status.p,
+            onesweep_dispatch<K, uint64_t, ROLE, VT>(tile, ki, vi, ko, vo, (uint32_t)n, sh, b, status.p,
                                                  ticket.as<uint32_t>(), s);
         inB = !inB;
     }
@@ -513,7 +520,11 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
     }
 
     DevBuf &rank = P->rank;
-    DevBuf kA, kB, vA, vB, kcount, nanflag, part, counts, bases, ppos;
+    DevBuf kA, kB, vA, vB, kcount, nanflag, part, counts, bases, ppos, pr;
+    // m = 2: the last axis is sorted with 64-bit payloads carrying each
+    // point's rank and record payload (extract_sigma_kernel), after the key
+    // layout is known; the count pass then reads them in sequence
+    const bool sigv = nax == 1;
     kA.alloc((size_t)n * sizeof(KP), s);
     kB.alloc((size_t)n * sizeof(KP), s);
     vA.alloc((size_t)n * 4, s);
@@ -523,7 +534,8 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
         kcount.alloc((size_t)nax * ni * 4, s);
         fill(kcount.as<uint32_t>(), (uint64_t)nax * ni, 0u, s);
         P->permuted = true;
-        ppos.alloc((size_t)n * 4, s);
+        if (nax == 1) pr.alloc((size_t)n * 8, s);
+        else ppos.alloc((size_t)n * 4, s);
         P->dinv.alloc((size_t)P->nD * 4, s);
         P->qinv.alloc((size_t)P->nQ * 4, s);
     }
@@ -542,7 +554,7 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
     scan_ticket.alloc(16, s);
 
     // expanded axes first, the real (last) axis last
-    for (int axis = 0; axis < m; ++axis) {
+    for (int axis = 0; axis < (sigv ? 1 : m); ++axis) {
         launch("extract_keys", s, [&] {
             extract_keys_kernel<KP, C, kBlock><<<ext_blocks, kBlock, 0, s>>>(
                 qq, dq, m, axis, nQ, n, inst_of_slot.as<uint32_t>(), axis > 0 ? ppos.as<uint32_t>() : nullptr,
@@ -573,6 +585,7 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
             rp.doff = P->batched ? doff_dev.as<int64_t>() : nullptr;
             rp.qoff = P->batched ? qoff_dev.as<int64_t>() : nullptr;
             rp.ppos = ppos.as<uint32_t>();
+            rp.pr = pr.as<uint64_t>();
             rp.dinv = P->dinv.as<uint32_t>();
             rp.qinv = P->qinv.as<uint32_t>();
             scan_launch<RankProblem<KP, true>, sizeof(KP) == 4 ? 16 : 8>(
@@ -624,6 +637,35 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
             P->key64 = fs >= 32;
         }
     }
+    DevBuf sig_vals64;
+    if (sigv) {
+        DevBuf wA, wB;
+        wA.alloc((size_t)n * 8, s);
+        wB.alloc((size_t)n * 8, s);
+        launch("extract_keys", s, [&] {
+            auto go = [&](auto *w) {
+                using W = std::remove_const_t<std::remove_pointer_t<decltype(w)>>;
+                extract_sigma_kernel<KP, C, W, kBlock><<<ext_blocks, kBlock, 0, s>>>(
+                    qq, dq, 1, nQ, n, inst_of_slot.as<uint32_t>(), pr.as<uint64_t>(), w, P->inline_w, kA.as<KP>(),
+                    wA.as<uint64_t>(), passes, part.as<uint32_t>(), nanflag.as<uint32_t>());
+            };
+            if (P->inline_w && P->w_dt == DOM_AGG_I32) go(static_cast<const int32_t *>(P->w_src));
+            else go(P->inline_w ? static_cast<const float *>(P->w_src) : static_cast<const float *>(nullptr));
+        });
+        reduce_hist(part.as<uint32_t>(), (int)ext_blocks, passes, counts.as<uint32_t>(), bases.as<uint32_t>(), s);
+        const size_t cb = (size_t)passes * kRadix * 4;
+        uint32_t *h = static_cast<uint32_t *>(hs.get(cb + 4));
+        HIPCHK(hipMemcpyAsync(h, counts.p, cb, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(h + passes * kRadix, nanflag.p, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (h[passes * kRadix]) fail(DOM_AGG_ENAN, "a coordinate on axis %d is NaN", m - 1);
+        const std::vector<int> shifts = live_shifts(h, passes, n);
+        const bool inB = radix_sort<KP, 0, uint64_t>(kA.as<KP>(), wA.as<uint64_t>(), kB.as<KP>(), wB.as<uint64_t>(),
+                                                  n, shifts, bases.as<uint32_t>(), P->tune.point_sort_tile, s);
+        sig_keys = std::move(inB ? kB : kA);
+        sig_vals64 = std::move(inB ? wB : wA);
+        pr.reset();
+    }
     // Key-length classes (one instance only: the instance bits of a batch sit
     // above every node id, so nearly all keys would share one class).
     if (!P->batched && nax >= 1) {
@@ -665,7 +707,7 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
     P->pay.alloc((size_t)n * 4, s);
     if (P->batched) P->inst_s.alloc((size_t)n * 4, s);
 
-    if (P->inline_w) {
+    if (P->inline_w && !sigv) {
         // first-axis rank and weight bits side by side: the count scan's one
         // gather per point fetches both
         P->rw.alloc((size_t)n * 8, s);
@@ -681,6 +723,23 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
                     P->rw.as<uint64_t>());
         });
     }
+    if (sigv && P->inline_w) P->wv.alloc((size_t)n * 4, s);
+    auto count_sigma = [&](auto inl_c) {
+        constexpr bool INL = decltype(inl_c)::value;
+        CountProblemSigma<KP, INL> cp{};
+        cp.keys = sig_keys.as<KP>();
+        cp.vals = sig_vals64.as<uint64_t>();
+        cp.ltab = P->ltab.as<uint8_t>();
+        cp.n_inst = (uint32_t)ni;
+        cp.n = n;
+        cp.off = P->off.as<uint64_t>();
+        cp.rs = P->rs.as<uint32_t>();
+        cp.pay = P->pay.as<uint32_t>();
+        cp.inst_s = P->inst_s.as<uint32_t>();
+        cp.wv = P->wv.as<uint32_t>();
+        scan_launch<CountProblemSigma<KP, INL>, 8>("count_scan", cp, n, scan_status.as<uint64_t>(),
+                                                   scan_status.bytes / 8, scan_ticket.as<uint32_t>(), s);
+    };
     auto count = [&](auto nax_c) {
         constexpr int NAX = decltype(nax_c)::value;
         auto go = [&](auto inl_c) {
@@ -696,12 +755,17 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
         if (NAX > 0 && P->inline_w) go(std::true_type{});
         else go(std::false_type{});
     };
-    switch (nax) {
-        case 0: count(std::integral_constant<int, 0>{}); break;
-        case 1: count(std::integral_constant<int, 1>{}); break;
-        case 2: count(std::integral_constant<int, 2>{}); break;
-        default: count(std::integral_constant<int, 3>{}); break;
+    if (sigv) {
+        if (P->inline_w) count_sigma(std::true_type{});
+        else count_sigma(std::false_type{});
+    } else {
+        switch (nax) {
+            case 0: count(std::integral_constant<int, 0>{}); break;
+            case 2: count(std::integral_constant<int, 2>{}); break;
+            default: count(std::integral_constant<int, 3>{}); break;
+        }
     }
+    sig_vals64.reset();
     uint64_t *h = static_cast<uint64_t *>(hs.get(8));
     HIPCHK(hipMemcpyAsync(h, P->off.as<uint64_t>() + n, 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));

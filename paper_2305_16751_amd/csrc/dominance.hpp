@@ -69,6 +69,58 @@ __global__ __launch_bounds__(BLOCK) void extract_keys_kernel(
     hist_flush(s_hist, hist_part, passes);
 }
 
+// m = 2: keys of the last (real) axis as above, with 64-bit payloads that
+// carry what the flat map needs of each point, so that the count pass reads
+// it in sequence instead of gathering it:
+//   bit 63 query, bits 32..62 first-axis rank, bits 0..31 the record payload
+//   (query: its internal row, with kQueryFlag unless records carry weights;
+//   data: its internal row, or its weight bits when records carry weights).
+// pr[s] = rank << 32 | internal slot (from the first axis's rank pass); w:
+// weights in input order (records carrying weights) or null.
+template <class K, class C, class W, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void extract_sigma_kernel(
+    const C *__restrict__ q, const C *__restrict__ d, int axis, uint32_t nQ, uint32_t n,
+    const uint32_t *__restrict__ inst_of_slot, const uint64_t *__restrict__ pr, const W *__restrict__ w,
+    bool carry_weights, K *__restrict__ keys, uint64_t *__restrict__ vals, int passes,
+    uint32_t *__restrict__ hist_part, uint32_t *__restrict__ nan_flag) {
+    __shared__ uint32_t s_hist[kMaxPasses * kRadix];
+    for (int i = threadIdx.x; i < passes * kRadix; i += BLOCK) s_hist[i] = 0;
+    __syncthreads();
+    bool saw_nan = false;
+    const uint64_t stride = (uint64_t)gridDim.x * BLOCK;
+    for (uint64_t b = (uint64_t)blockIdx.x * BLOCK; b < n; b += stride) {
+        const uint64_t s = b + threadIdx.x;
+        const bool valid = s < n;
+        K key = 0;
+        if (valid) {
+            const bool isq = s < nQ;
+            const C x = isq ? q[s * 2 + axis] : d[(s - nQ) * 2 + axis];
+            saw_nan |= is_nan(x);
+            key = (K)ordered_key(x);
+            if constexpr (sizeof(K) == 8) {
+                if (inst_of_slot) key |= (K)inst_of_slot[s] << 32;
+            }
+            const uint64_t rs = pr[s];
+            const uint32_t sp = (uint32_t)rs, r = (uint32_t)(rs >> 32);
+            uint32_t payload;
+            if (isq) {
+                payload = carry_weights ? sp : (kQueryFlag | sp);
+            } else if (carry_weights) {
+                payload = 0;
+                if (w) __builtin_memcpy(&payload, &w[s - nQ], 4);
+            } else {
+                payload = sp - nQ;
+            }
+            keys[s] = key;
+            vals[s] = ((uint64_t)((isq ? 0x80000000u : 0u) | r) << 32) | payload;
+        }
+        hist_add(s_hist, key, valid, passes);
+    }
+    if (saw_nan) atomicOr(nan_flag, 1u);
+    __syncthreads();
+    hist_flush(s_hist, hist_part, passes);
+}
+
 // inst_of_slot[s]: the instance owning slot s (largest k with off[k] <= row).
 __global__ void instance_of_slot_kernel(const int64_t *__restrict__ q_off,
                                         const int64_t *__restrict__ d_off, int64_t n_inst,
@@ -136,7 +188,8 @@ struct RankProblem {
     // POS only
     uint32_t nQ;
     const int64_t *doff, *qoff;  // instance offsets of data and queries, or null (one instance)
-    uint32_t *ppos;              // [n] by input slot: the internal slot
+    uint32_t *ppos;              // [n] by input slot: the internal slot (or null, see pr)
+    uint64_t *pr;                // or [n] by input slot: rank << 32 | internal slot (m = 2)
     uint32_t *dinv, *qinv;       // [nD], [nQ]: input row of each position
 
     __device__ static uint32_t inst(const Raw &r) {
@@ -174,7 +227,8 @@ struct RankProblem {
                 qinv[p] = cur.slot;
                 sp = p;
             }
-            ppos[cur.slot] = sp;
+            if (pr) pr[cur.slot] = ((uint64_t)r << 32) | sp;
+            else ppos[cur.slot] = sp;
             rank[sp] = r;
         } else {
             rank[cur.slot] = r;
@@ -292,6 +346,57 @@ struct CountProblem {
 // (1 << j) | (r >> (L_a - j)), which is unique across lengths.  Points are in
 // last-axis order and the record sort is stable, which yields the Sec. 5
 // order inside every segment.
+
+// m = 2 with the last-axis sort's 64-bit payloads (extract_sigma_kernel):
+// the same counts, offsets and laid-out state, read in sequence.
+template <class K, bool INL>
+struct CountProblemSigma {
+    using V = uint64_t;
+    struct Raw {
+        K key;
+        uint64_t v;
+    };
+    const K *keys;
+    const uint64_t *vals;
+    const uint8_t *ltab;  // [n_inst]
+    uint32_t n_inst, n;
+    uint64_t *off;        // [n + 1]
+    uint32_t *rs;         // [n] by position: first-axis rank
+    uint32_t *pay;        // [n] by position: kQueryFlag | query row, or data row (0 with weights)
+    uint32_t *inst_s;     // [n] by position, or null
+    uint32_t *wv;         // INL: [n] by position, weight bits of data points
+
+    __device__ static uint32_t inst(const Raw &r) {
+        if constexpr (sizeof(K) == 8) return (uint32_t)(r.key >> 32);
+        else return 0u;
+    }
+    __device__ V identity() const { return 0ull; }
+    __device__ V combine(V a, V b) const { return a + b; }
+    __device__ Raw load(uint64_t i) const { return Raw{keys[i], vals[i]}; }
+    __device__ bool head(const Raw &, const Raw &) const { return false; }
+    __device__ V value(const Raw &, bool, const Raw &cur, uint64_t i) const {
+        const bool isq = (cur.v >> 63) != 0;
+        const uint32_t r = (uint32_t)(cur.v >> 32) & 0x7fffffffu;
+        const uint32_t payload = (uint32_t)cur.v;
+        const uint32_t ins = inst(cur);
+        if (ins >= n_inst) return 0ull;  // only if the sort were wrong: no records
+        const uint32_t L = ltab[ins];
+        const uint32_t pc = (uint32_t)__popc(r);
+        rs[i] = r;
+        if (isq) {
+            pay[i] = kQueryFlag | (payload & ~kQueryFlag);
+        } else {
+            pay[i] = INL ? 0u : payload;
+            if (INL) wv[i] = payload;
+        }
+        if (inst_s) inst_s[i] = ins;
+        return isq ? pc : (L - pc);
+    }
+    __device__ void emit(uint64_t i, const Raw &, V, V excl, V incl, bool) const {
+        off[i] = excl;
+        if (i == (uint64_t)n - 1) off[n] = incl;
+    }
+};
 
 // Key-length classes.  The sort only has to bring equal keys together (any
 // order of the segments will do) and keep the last-axis order inside them.

@@ -143,11 +143,12 @@ struct DigitWord {
 // launch; ticket: zero before the launch.  digit_base: [256] exclusive bases
 // of the pass's digits over the whole array.  ROLE only names the
 // instantiation (0: per-point coordinate sorts, 1: the sort of the expanded
-// records) so the two show up separately in profiles.
-template <class K, class S, int BLOCK, int ITEMS, int ROLE = 0>
+// records) so the two show up separately in profiles.  VT: the payload type
+// (u32, or u64 for the last-axis sort that carries each point's rank).
+template <class K, class S, int BLOCK, int ITEMS, int ROLE = 0, class VT = uint32_t>
 __global__ __launch_bounds__(BLOCK) void onesweep_kernel(
-    const K *__restrict__ kin, const uint32_t *__restrict__ vin, K *__restrict__ kout,
-    uint32_t *__restrict__ vout, uint32_t n, int shift, const uint32_t *__restrict__ digit_base,
+    const K *__restrict__ kin, const VT *__restrict__ vin, K *__restrict__ kout,
+    VT *__restrict__ vout, uint32_t n, int shift, const uint32_t *__restrict__ digit_base,
     S *__restrict__ status, uint32_t *__restrict__ ticket) {
     constexpr int TILE = BLOCK * ITEMS;
     constexpr int WAVES = BLOCK / kWave;
@@ -157,7 +158,7 @@ __global__ __launch_bounds__(BLOCK) void onesweep_kernel(
 
     __shared__ union {
         K keys[TILE];
-        uint32_t vals[TILE];
+        VT vals[TILE];
     } s_stage;
     __shared__ uint32_t s_whist[WAVES][kRadix];  // counts, then exclusive over waves
     __shared__ uint32_t s_dstart[kRadix];        // tile-local start of each digit
@@ -175,7 +176,7 @@ __global__ __launch_bounds__(BLOCK) void onesweep_kernel(
     // Wave-striped loads: item i of lane l is element wbase + 64 i + l, so
     // ranking items in order i keeps index order within the wavefront.
     K key[ITEMS];
-    uint32_t val[ITEMS];
+    VT val[ITEMS];
     uint32_t loc[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
@@ -185,7 +186,7 @@ __global__ __launch_bounds__(BLOCK) void onesweep_kernel(
             val[i] = vin[idx];
         } else {
             key[i] = ~K(0);  // digit 255 at every shift: sorts after all real keys of the tile
-            val[i] = 0;
+            val[i] = VT(0);
         }
     }
 
