@@ -150,7 +150,29 @@ def run_plain(case, steps, warmup, op="sum"):
     return T, kern, info, out
 
 
-def roofline_entry(kern, info):
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, calibrated on a plain copy), or None
+    when there is none for this kernel or its sources changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{workload}_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    rec = None
+    for line in open(path):
+        if line.startswith("traffic-record:"):
+            rec = dict(kv.split("=", 1) for kv in line.split(":", 1)[1].split())
+    if not rec or rec.get("kernel") != kernel:
+        return None
+    h = hashlib.sha256()
+    for f in ("radix_sort.hpp", "device_common.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2305_16751_amd", "csrc", f), "rb").read())
+    if h.hexdigest() != rec.get("sources_sha256"):
+        return None
+    return int(rec["bytes_per_launch"])
+
+
+def roofline_entry(kern, info, workload=None):
     rec = {k: v for k, v in kern.items() if k.startswith("onesweep_records")}
     if not rec:
         return None
@@ -160,7 +182,8 @@ def roofline_entry(kern, info):
     b = tot / launches
     ach = b / avg_s / 1e9
     return {"bound": "hbm", "kernel": name, "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None,
+            "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": measured_traffic(name, workload) if workload else None,
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "bytes_per_launch": round(b), "avg_launch_ms": round(avg_s * 1e3, 5),
             "bytes_model": "sum over key-length classes of passes_c * 2 * E_c * (key bytes + 4 payload bytes) "
                            "(every record of a class read and written once per pass of its class), "
@@ -310,7 +333,7 @@ def main():
                    "weights": "float32 N(0,1)", "records": info["records"], "key_bits": info["key_bits"],
                    "sort_passes": info["sort_passes"], "sort_classes": info["sort_classes"], "sort_tile": info["sort_tile"],
                    "scan_tile": info["scan_tile"], "step": "dom_agg_run (plan + forward in one call)"},
-        "roofline": roofline_entry(kern, info),
+        "roofline": roofline_entry(kern, info, case.name),
     }
     extra = {"stages": stage_table(kern, args.steps, info, case.n, case.m - 1)}
     if not args.no_cpu_baseline:
