@@ -284,6 +284,10 @@ struct dom_agg_plan_s {
     // each data / query position, and a buffer for inputs in that order
     bool permuted = false;
     DevBuf dinv, qinv, perm;
+    // m = 2, one instance: rank CDFs of data and queries (the record sort's
+    // digit histograms are counted from them per tree node)
+    DevBuf cdf_d, cdf_q;
+    uint32_t K0 = 0;
     // records carrying weights (one-shot calls): requested, granted, the
     // query flag's bit in the record key, the weights and their dtype
     bool inline_req = false, inline_w = false;
@@ -309,7 +313,7 @@ struct dom_agg_plan_s {
 
     size_t workspace() const {
         return off.bytes + rs.bytes + pay.bytes + inst_s.bytes + rank.bytes + inst_of_slot.bytes + ltab.bytes +
-               dinv.bytes + qinv.bytes + perm.bytes + rw.bytes + wv.bytes + part.bytes + rkeys.bytes + rvals.bytes + scan_status.bytes + scan_ticket.bytes + ed_counter.bytes;
+               dinv.bytes + qinv.bytes + perm.bytes + rw.bytes + wv.bytes + cdf_d.bytes + cdf_q.bytes + part.bytes + rkeys.bytes + rvals.bytes + scan_status.bytes + scan_ticket.bytes + ed_counter.bytes;
     }
     SlotMap slot_map() const {
         SlotMap sm{};
@@ -536,6 +540,10 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
         P->permuted = true;
         if (nax == 1) pr.alloc((size_t)n * 8, s);
         else ppos.alloc((size_t)n * 4, s);
+        if (nax == 1 && !P->batched) {
+            P->cdf_d.alloc((size_t)n * 4, s);
+            P->cdf_q.alloc((size_t)n * 4, s);
+        }
         P->dinv.alloc((size_t)P->nD * 4, s);
         P->qinv.alloc((size_t)P->nQ * 4, s);
     }
@@ -586,6 +594,8 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
             rp.qoff = P->batched ? qoff_dev.as<int64_t>() : nullptr;
             rp.ppos = ppos.as<uint32_t>();
             rp.pr = pr.as<uint64_t>();
+            rp.cdf_d = P->cdf_d.as<uint32_t>();
+            rp.cdf_q = P->cdf_q.as<uint32_t>();
             rp.dinv = P->dinv.as<uint32_t>();
             rp.qinv = P->qinv.as<uint32_t>();
             scan_launch<RankProblem<KP, true>, sizeof(KP) == 4 ? 16 : 8>(
@@ -609,6 +619,7 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
         uint32_t *h = static_cast<uint32_t *>(hs.get((size_t)nax * ni * 4));
         HIPCHK(hipMemcpyAsync(h, kcount.p, (size_t)nax * ni * 4, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
+        P->K0 = h[0];
         for (int a = 0; a < nax; ++a) {
             int lm = 0;
             for (int64_t k = 0; k < ni; ++k) {
@@ -839,6 +850,23 @@ void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &ou
         a.cls_row0[q] = P->cls_row0[q];
         a.cls_mask[q] = P->cls_mask[q];
     }
+    // m = 2 with classes: the digit histograms come from the rank CDFs, one
+    // thread per tree node, instead of one update per record in the flat map
+    const bool node_hist = cls && P->cdf_d.p && P->m == 2;
+    DevBuf npart;
+    unsigned ngrid = 0;
+    if (node_hist) {
+        const uint64_t nodes = 1ull << P->Lmax[0];
+        ngrid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(ceil_div(nodes, kBlock), 2048));
+        npart.alloc((size_t)ngrid * rows * kRadix * 4, s);
+        EmitArgs na = a;
+        na.hist_part = npart.as<uint32_t>();
+        launch("node_hist", s, [&] {
+            node_hist_kernel<<<ngrid, kBlock, 0, s>>>(P->cdf_d.as<uint32_t>(), P->cdf_q.as<uint32_t>(), P->K0,
+                                                     (uint32_t)P->nD, (uint32_t)P->nQ, P->Lmax[0], na);
+        });
+        a.hist_part = nullptr;  // the flat map skips its histograms
+    }
     auto per_nax = [&](auto &&f) {
         switch (P->nax) {
             case 0: f(std::integral_constant<int, 0>{}); break;
@@ -893,7 +921,8 @@ void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &ou
                                                                                    nullptr, nullptr);
         });
     });
-    reduce_hist(part.as<uint32_t>(), (int)grid, rows, counts.as<uint32_t>(), bases.as<uint32_t>(), s);
+    if (node_hist) reduce_hist(npart.as<uint32_t>(), (int)ngrid, rows, counts.as<uint32_t>(), bases.as<uint32_t>(), s);
+    else reduce_hist(part.as<uint32_t>(), (int)grid, rows, counts.as<uint32_t>(), bases.as<uint32_t>(), s);
     if (probe) {
         const size_t cb = (size_t)rows * kRadix * 4;
         uint32_t *h = static_cast<uint32_t *>(hs->get(cb + 12));
@@ -1350,6 +1379,8 @@ std::unique_ptr<Plan> make_plan(int m, dom_agg_dtype coord_dtype, const void *d_
                 P->off.reset();
                 P->rw.reset();
                 P->wv.reset();
+                P->cdf_d.reset();
+                P->cdf_q.reset();
             }
         }
         HIPCHK(hipStreamSynchronize(s));

@@ -190,6 +190,7 @@ struct RankProblem {
     const int64_t *doff, *qoff;  // instance offsets of data and queries, or null (one instance)
     uint32_t *ppos;              // [n] by input slot: the internal slot (or null, see pr)
     uint64_t *pr;                // or [n] by input slot: rank << 32 | internal slot (m = 2)
+    uint32_t *cdf_d, *cdf_q;     // or null; one instance: data / queries of rank below r, at [r]
     uint32_t *dinv, *qinv;       // [nD], [nQ]: input row of each position
 
     __device__ static uint32_t inst(const Raw &r) {
@@ -205,11 +206,17 @@ struct RankProblem {
         if constexpr (POS) return distinct | ((uint64_t)(cur.slot >= nQ) << 32);
         else return distinct;
     }
-    __device__ void emit(uint64_t i, const Raw &cur, V, V, V incl, bool last) const {
+    __device__ void emit(uint64_t i, const Raw &cur, V v, V excl, V incl, bool last) const {
         const uint32_t r = (uint32_t)incl - 1u;
         const uint32_t ins = inst(cur);
         if (cur.slot >= n || ins >= n_inst) return;  // only if the sort were wrong
         if constexpr (POS) {
+            if (cdf_d && ((uint32_t)v & 1u) && r < n) {
+                // the first point of rank r: the points before it have ranks below r
+                const uint32_t dbefore = (uint32_t)(excl >> 32);
+                cdf_d[r] = dbefore;
+                cdf_q[r] = (uint32_t)i - dbefore;
+            }
             // data points up to and including element i, in this instance
             const uint64_t cd = incl >> 32;
             const uint64_t dbase = doff ? (uint64_t)doff[ins] : 0ull;
@@ -615,6 +622,47 @@ __global__ __launch_bounds__(256) void class_count_kernel(EmitArgs a, unsigned l
     if (threadIdx.x < kMaxClasses && s_tot[threadIdx.x]) atomicAdd(cls_tot + threadIdx.x, s_tot[threadIdx.x]);
 }
 
+// m = 2, one instance: the digit histograms of the record keys of every
+// class and pass, without looking at a single record.  The records of tree
+// node t = (1 << j) | P are the data points whose rank has prefix P then a
+// 0 digit and the queries whose rank has prefix P then a 1 digit (Lemma 2's
+// prefix sets), i.e. two rank ranges, counted from the rank CDFs: cdf_d[x] =
+// data points of rank below x (x < K; nD from K on), cdf_q likewise.  Rows
+// of the histogram as in the flat map: class q, pass p -> row0[q] + p.
+__global__ __launch_bounds__(256) void node_hist_kernel(const uint32_t *__restrict__ cdf_d,
+                                                        const uint32_t *__restrict__ cdf_q, uint32_t K, uint32_t nD,
+                                                        uint32_t nQ, int L, EmitArgs a) {
+    __shared__ uint32_t s_hist[26 * kRadix];
+    const int rows = a.hist_rows;
+    for (int i = threadIdx.x; i < rows * kRadix; i += blockDim.x) s_hist[i] = 0;
+    __syncthreads();
+    auto cd = [&](uint64_t x) { return x < K ? cdf_d[x] : nD; };
+    auto cq = [&](uint64_t x) { return x < K ? cdf_q[x] : nQ; };
+    const uint64_t nodes = 1ull << L;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x + 1; t < nodes; t += stride) {
+        const int j = 63 - __clzll((long long)t);
+        const uint64_t P = t ^ (1ull << j);
+        const uint64_t half = 1ull << (L - j - 1);
+        const uint64_t lo = P << (L - j);
+        const uint32_t cnt = (cd(lo + half) - cd(lo)) + (cq(lo + 2 * half) - cq(lo + half));
+        if (cnt == 0) continue;
+        const int q = key_class((uint32_t)t, a.cls_c0);
+        int row0 = 0;
+#pragma unroll
+        for (int c = 0; c < kMaxClasses; ++c)
+            if (c < q) row0 += a.cls_passes[c];
+        int np = a.cls_passes[0];
+#pragma unroll
+        for (int c = 1; c < kMaxClasses; ++c)
+            if (c == q) np = a.cls_passes[c];
+        for (int p = 0; p < np; ++p)
+            atomicAdd(&s_hist[(row0 + p) * kRadix + ((uint32_t)(t >> (kRadixBits * p)) & (kRadix - 1))], cnt);
+    }
+    __syncthreads();
+    if (rows) hist_flush(s_hist, a.hist_part, rows);
+}
+
 // The flat map (Sec. 4 with Sec. 5).  Record o belongs to the point k with
 // off[k] <= o < off[k+1]; its index t = o - off[k] enumerates the product of
 // the point's per-axis prefix sets, last expanded axis fastest.  On axis a
@@ -698,7 +746,8 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(EmitArgs a, K *__restrict__
     __shared__ uint64_t s_scan[BLOCK / kWave];
     __shared__ uint64_t s_cdst[kMaxClasses];  // destination of the chunk's first slot of each class, minus its run start
     __shared__ uint32_t s_chunk;
-    const int rows = CLS ? a.hist_rows : a.passes;
+    // (with classes the histograms may come from elsewhere: hist_part null)
+    const int rows = a.hist_part ? (CLS ? a.hist_rows : a.passes) : 0;
     for (int i = threadIdx.x; i < rows * kRadix; i += BLOCK) s_hist[i] = 0;
     if (threadIdx.x == 0) s_data = 0;
     uint32_t my_data = 0;
@@ -833,11 +882,11 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(EmitArgs a, K *__restrict__
                 }
             }
             if constexpr (!CLS) {
-                hist_add(s_hist, key, valid, a.passes, peel_from);
+                if (rows) hist_add(s_hist, key, valid, a.passes, peel_from);
             } else {
                 const int q = valid ? key_class(key & kmask, a.cls_c0) : 0;
                 const uint32_t ci = (uint32_t)(cls_info >> (16 * q));
-                hist_add_rows(s_hist, key, valid, (int)(ci & 0xffu), (int)((ci >> 8) & 0xffu), a.passes);
+                if (rows) hist_add_rows(s_hist, key, valid, (int)(ci & 0xffu), (int)((ci >> 8) & 0xffu), a.passes);
             }
         }
         if constexpr (CLS) {
@@ -918,7 +967,7 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(EmitArgs a, K *__restrict__
         }
     }
     __syncthreads();
-    hist_flush(s_hist, a.hist_part, rows);
+    if (rows) hist_flush(s_hist, a.hist_part, rows);
     if (my_data) atomicAdd(&s_data, (unsigned long long)my_data);
     __syncthreads();
     if (threadIdx.x == 0 && s_data) atomicAdd(a.data_records, s_data);
