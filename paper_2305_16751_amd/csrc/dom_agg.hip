@@ -354,6 +354,18 @@ unsigned grid_for(uint64_t n) {
     return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(ceil_div(n, kBlock), 8192));
 }
 
+// Workgroups of `kernel` (kBlock threads) resident on the current device at
+// once, at most `work`.
+template <class F>
+unsigned resident_grid(F kernel, uint64_t work) {
+    int dev = 0, cus = 0, per = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kBlock, 0));
+    const uint64_t g = (uint64_t)std::max(per, 1) * (uint64_t)std::max(cus, 1);
+    return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(g, work));
+}
+
 template <class T>
 void fill(T *p, uint64_t n, T v, hipStream_t s) {
     if (!n) return;
@@ -811,7 +823,26 @@ void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &ou
     constexpr int CHUNK_SHIFT = 11;
     static_assert((1 << CHUNK_SHIFT) == CHUNK, "");
     const uint64_t nchunks = ceil_div(E, CHUNK);
-    const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(nchunks, 4096));
+    auto per_nax = [&](auto &&f) {
+        switch (P->nax) {
+            case 0: f(std::integral_constant<int, 0>{}); break;
+            case 1: f(std::integral_constant<int, 1>{}); break;
+            case 2: f(std::integral_constant<int, 2>{}); break;
+            default: f(std::integral_constant<int, 3>{}); break;
+        }
+    };
+    // m = 2 with classes: the digit histograms come from the rank CDFs, one
+    // thread per tree node, instead of one update per record in the flat map
+    const bool node_hist = cls && P->cdf_d.p && P->m == 2;
+    // the flat map's workgroups: as many as are resident at once (each takes
+    // a fixed share of the chunks)
+    unsigned grid = 1;
+    per_nax([&](auto nax_c) {
+        constexpr int NAX = decltype(nax_c)::value;
+        if (node_hist) grid = resident_grid(emit_kernel<K, NAX, kBlock, EITEMS, true, false>, nchunks);
+        else if (cls) grid = resident_grid(emit_kernel<K, NAX, kBlock, EITEMS, true>, nchunks);
+        else grid = resident_grid(emit_kernel<K, NAX, kBlock, EITEMS, false>, nchunks);
+    });
     DevBuf chunk_k;
     chunk_k.alloc(nchunks * 4, s);
     launch("chunk_start", s, [&] {
@@ -850,9 +881,6 @@ void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &ou
         a.cls_row0[q] = P->cls_row0[q];
         a.cls_mask[q] = P->cls_mask[q];
     }
-    // m = 2 with classes: the digit histograms come from the rank CDFs, one
-    // thread per tree node, instead of one update per record in the flat map
-    const bool node_hist = cls && P->cdf_d.p && P->m == 2;
     DevBuf npart;
     unsigned ngrid = 0;
     if (node_hist) {
@@ -867,25 +895,34 @@ void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &ou
         });
         a.hist_part = nullptr;  // the flat map skips its histograms
     }
-    auto per_nax = [&](auto &&f) {
-        switch (P->nax) {
-            case 0: f(std::integral_constant<int, 0>{}); break;
-            case 1: f(std::integral_constant<int, 1>{}); break;
-            case 2: f(std::integral_constant<int, 2>{}); break;
-            default: f(std::integral_constant<int, 3>{}); break;
-        }
-    };
     if (cls) {
-        if (probe) {
-            DevBuf tot;
-            tot.alloc(kMaxClasses * 8, s);
-            fill(tot.as<unsigned long long>(), kMaxClasses, 0ull, s);
-            per_nax([&](auto nax_c) {
-                constexpr int NAX = decltype(nax_c)::value;
-                launch("class_count", s, [&] {
-                    class_count_kernel<NAX><<<grid_for(P->n), kBlock, 0, s>>>(a, tot.as<unsigned long long>());
-                });
+        // Records of each class per chunk (closed form over the points), their
+        // exclusive sums over the chunks (each chunk's class offsets, so the
+        // emitter's chunks never wait on each other) and the class totals.
+        static_assert(kBlock == 256, "chunk kernels use 256-thread workgroups");
+        const uint64_t ngroups = ceil_div(nchunks, (uint64_t)kChunkGroup);
+        DevBuf ccnt, gsum, tot;
+        ccnt.alloc(nchunks * 8, s);
+        gsum.alloc(ngroups * 16, s);
+        tot.alloc(kMaxClasses * 8, s);
+        cstat.alloc(nchunks * 16, s);
+        fill(ccnt.as<unsigned long long>(), nchunks, 0ull, s);
+        per_nax([&](auto nax_c) {
+            constexpr int NAX = decltype(nax_c)::value;
+            launch("chunk_class", s, [&] {
+                chunk_class_kernel<NAX><<<grid_for(P->n), kBlock, 0, s>>>(a, CHUNK_SHIFT, ccnt.as<unsigned long long>());
             });
+        });
+        launch("chunk_offsets", s, [&] {
+            chunk_group_kernel<<<(unsigned)ngroups, kBlock, 0, s>>>(ccnt.as<unsigned long long>(), nchunks,
+                                                                    gsum.as<unsigned long long>());
+        });
+        launch("chunk_offsets", s, [&] {
+            chunk_offsets_kernel<<<(unsigned)ngroups, kBlock, 0, s>>>(
+                ccnt.as<unsigned long long>(), gsum.as<unsigned long long>(), nchunks, cstat.as<uint4>(),
+                tot.as<unsigned long long>());
+        });
+        if (probe) {
             uint64_t *h = static_cast<uint64_t *>(hs->get(kMaxClasses * 8));
             HIPCHK(hipMemcpyAsync(h, tot.p, kMaxClasses * 8, hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
@@ -902,18 +939,18 @@ void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &ou
             a.cls_base[q] = base;
             base += P->cls_tot[q];
         }
-        cstat.alloc(nchunks * kMaxClasses * 8, s);
     }
     ticket.alloc(16, s);
-    clear_lookback(cstat.as<uint64_t>(), cls ? nchunks * kMaxClasses : 0, ticket.as<uint32_t>(), s);
-    fill(ticket.as<uint32_t>() + 1, 1, 0u, s);
-    a.cls_status = cstat.as<unsigned long long>();
-    a.ticket = ticket.as<uint32_t>();
+    fill(ticket.as<uint32_t>(), 2, 0u, s);  // (word 1: the error flag)
+    a.cls_off = cstat.as<uint32_t>();
     a.error = ticket.as<uint32_t>() + 1;
     per_nax([&](auto nax_c) {
         constexpr int NAX = decltype(nax_c)::value;
         launch("flatmap_emit", s, [&] {
-            if (cls)
+            if (cls && !a.hist_part)
+                emit_kernel<K, NAX, kBlock, EITEMS, true, false><<<grid, kBlock, 0, s>>>(
+                    a, kA.as<K>(), vA.as<uint32_t>(), kB.as<K>(), vB.as<uint32_t>());
+            else if (cls)
                 emit_kernel<K, NAX, kBlock, EITEMS, true><<<grid, kBlock, 0, s>>>(a, kA.as<K>(), vA.as<uint32_t>(),
                                                                                   kB.as<K>(), vB.as<uint32_t>());
             else

@@ -438,8 +438,7 @@ struct EmitArgs {
     int hist_rows;                       // sum of cls_passes
     uint64_t cls_base[kMaxClasses];      // region starts
     uint32_t cls_mask[kMaxClasses];      // first-axis levels of each class (bit L-1-j for level j)
-    unsigned long long *cls_status;      // [chunks][kMaxClasses] look-back words
-    uint32_t *ticket;
+    const uint32_t *cls_off;             // [chunks][kMaxClasses]: records of each class before the chunk
     uint32_t *error;                     // set when a chunk's records disagree with its class counts
     // records carrying weights (flag_shift >= 0): a data record's payload is
     // its weight bits wv[k]; a query record's payload is its row and its key
@@ -476,8 +475,8 @@ __global__ void chunk_start_kernel(const uint64_t *__restrict__ off, uint32_t n,
 // Per-point state of the walk, cached in LDS for the points of one chunk.
 template <int NAX>
 struct PointCache {
-    static constexpr int kCap = 512;
-    uint32_t off[kCap + 1];  // record offsets relative to the chunk's first point
+    static constexpr int kCap = 480;  // (points per chunk: about CHUNK / 12 for uniform inputs)
+    uint32_t off[kCap + 1];  // low words of the record offsets (taken relative to off[0])
     uint32_t pay[kCap];
     uint32_t wv[kCap];
     uint32_t inst[kCap];
@@ -494,21 +493,25 @@ struct PointWalk {
     uint32_t payload, inst;  // payload: what the point's records carry
     bool isq;
 
-    __device__ void set(const EmitArgs &a, uint32_t pay, uint32_t wbits, uint32_t ins, const uint32_t *ranks) {
+    // lsingle: the levels of every axis (8 bits each) when there is one
+    // instance, else ~0u (then they are read per point)
+    __device__ void set(const EmitArgs &a, uint32_t pay, uint32_t wbits, uint32_t ins, const uint32_t *ranks,
+                        uint32_t lsingle) {
         isq = (pay & kQueryFlag) != 0u;
         payload = a.flag_shift < 0 ? pay : (isq ? (pay & ~kQueryFlag) : wbits);
         inst = ins;
 #pragma unroll
         for (int ax = 0; ax < NAX; ++ax) {
             r[ax] = ranks[ax];
-            L[ax] = a.ltab[(uint64_t)ax * a.n_inst + inst];
+            L[ax] = lsingle != ~0u ? (lsingle >> (8 * ax)) & 0xffu : a.ltab[(uint64_t)ax * a.n_inst + inst];
             const uint32_t mask = (L[ax] >= 32u) ? 0xffffffffu : ((1u << L[ax]) - 1u);
             full[ax] = isq ? (r[ax] & mask) : (~r[ax] & mask);
             rem[ax] = full[ax];
         }
     }
     // point k of the chunk (index idx among its points), from the LDS cache or global memory
-    __device__ void load(const EmitArgs &a, const PointCache<NAX> *pc, bool cached, uint32_t klo, uint32_t idx) {
+    __device__ void load(const EmitArgs &a, const PointCache<NAX> *pc, bool cached, uint32_t klo, uint32_t idx,
+                         uint32_t lsingle) {
         uint32_t rk[3] = {0, 0, 0};
         uint32_t pay, wb, ins;
         if (cached) {
@@ -525,7 +528,7 @@ struct PointWalk {
 #pragma unroll
             for (int ax = 0; ax < NAX; ++ax) rk[ax] = a.rs[(uint64_t)ax * a.n + k];
         }
-        set(a, pay, wb, ins, rk);
+        set(a, pay, wb, ins, rk, lsingle);
     }
     // positions the walk at the point's t-th record
     __device__ void seek(uint32_t t) {
@@ -599,29 +602,6 @@ __device__ __forceinline__ uint64_t point_class_counts(const EmitArgs &a, uint32
     return packed;
 }
 
-// Records per class over all points (one instance).
-template <int NAX>
-__global__ __launch_bounds__(256) void class_count_kernel(EmitArgs a, unsigned long long *__restrict__ cls_tot) {
-    __shared__ unsigned long long s_tot[kMaxClasses];
-    if (threadIdx.x < kMaxClasses) s_tot[threadIdx.x] = 0;
-    __syncthreads();
-    unsigned long long acc[kMaxClasses] = {0, 0, 0, 0};
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.n; k += stride) {
-        uint32_t rk[NAX > 0 ? NAX : 1];
-#pragma unroll
-        for (int ax = 0; ax < NAX; ++ax) rk[ax] = a.rs[(uint64_t)ax * a.n + k];
-        const uint64_t pc = point_class_counts<NAX>(a, a.pay[k], rk, 0u, 0xffffffffu);
-#pragma unroll
-        for (int q = 0; q < kMaxClasses; ++q) acc[q] += (pc >> (16 * q)) & 0xffffu;
-    }
-#pragma unroll
-    for (int q = 0; q < kMaxClasses; ++q)
-        if (acc[q]) atomicAdd(&s_tot[q], acc[q]);
-    __syncthreads();
-    if (threadIdx.x < kMaxClasses && s_tot[threadIdx.x]) atomicAdd(cls_tot + threadIdx.x, s_tot[threadIdx.x]);
-}
-
 // m = 2, one instance: the digit histograms of the record keys of every
 // class and pass, without looking at a single record.  The records of tree
 // node t = (1 << j) | P are the data points whose rank has prefix P then a
@@ -673,18 +653,18 @@ __global__ __launch_bounds__(256) void node_hist_kernel(const uint32_t *__restri
 // last-axis order and the record sort is stable, which yields the Sec. 5
 // order inside every segment.
 //
-// A block takes a chunk of CHUNK consecutive records (from a ticket, so that
-// every chunk it waits on is held by a running block) and loads the state of
-// the chunk's points into LDS with coalesced reads.  Each thread produces
-// ITEMS consecutive records (one search for its first, then a walk) and
-// stages them in LDS.  Without classes the block then writes them out in
-// place.  With classes, each thread first counts its records per class from
-// its points (closed form, see point_class_counts); one block scan of those
-// counts gives every record its slot in a class-split staging and the
-// chunk's counts, which are published before the walk.  After the walk,
-// wavefront 0 looks back over earlier chunks for each class's offset and the
-// block writes each class's run into its region.  The digit histograms of
-// every pass (of every class) are accumulated on the way.
+// A block takes chunks of CHUNK consecutive records (a fixed share of them)
+// and loads the state of each chunk's points into LDS with coalesced
+// reads.  Each thread produces ITEMS consecutive records (one
+// search for its first, then a walk) and stages them in LDS.  Without
+// classes the block then writes them out in place.  With classes, each
+// thread first counts its records per class from its points (closed form,
+// see point_class_counts); one block scan of those counts gives every record
+// its slot in a class-split staging, and the block writes each class's run
+// into its region at the chunk's class offset, computed beforehand for every
+// chunk by chunk_class_kernel and chunk_offsets_kernel.  The digit
+// histograms of every pass (of every class) are accumulated on the way, or
+// come from node_hist_kernel.
 
 // Adds the digits of `key` for passes [0, np) to histogram rows row0 + p;
 // lanes sharing the first active lane's row and digit are added with one
@@ -710,12 +690,14 @@ __device__ __forceinline__ void hist_add_rows(uint32_t *s_hist, K key, bool vali
 template <int BLOCK>
 __device__ __forceinline__ uint64_t block_excl_sum_packed(uint64_t v, uint64_t *s_tmp, uint64_t *total) {
     const int lane = lane_id(), wave = threadIdx.x / kWave;
+    // inclusive wavefront sum by DPP moves (rows, then across rows)
     uint64_t incl = v;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const uint64_t o = read_lane_u64(incl, lane >= d ? lane - d : 0);
-        if (lane >= d) incl += o;
-    }
+    incl += dpp_val<kDppRowShr1, 0xf>(incl, (uint64_t)0);
+    incl += dpp_val<kDppRowShr2, 0xf>(incl, (uint64_t)0);
+    incl += dpp_val<kDppRowShr4, 0xf>(incl, (uint64_t)0);
+    incl += dpp_val<kDppRowShr8, 0xf>(incl, (uint64_t)0);
+    incl += dpp_val<kDppRowBcast15, 0xa>(incl, (uint64_t)0);
+    incl += dpp_val<kDppRowBcast31, 0xc>(incl, (uint64_t)0);
     if (lane == kWave - 1) s_tmp[wave] = incl;
     __syncthreads();
     uint64_t pre = 0, tot = 0;
@@ -730,24 +712,187 @@ __device__ __forceinline__ uint64_t block_excl_sum_packed(uint64_t v, uint64_t *
     return pre + incl - v;
 }
 
-template <class K, int NAX, int BLOCK, int ITEMS, bool CLS>
+// Sum of `v` over the wavefront, in every lane (every lane must be active).
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+    v += dpp_val<kDppRowShr1, 0xf>(v, (uint64_t)0);
+    v += dpp_val<kDppRowShr2, 0xf>(v, (uint64_t)0);
+    v += dpp_val<kDppRowShr4, 0xf>(v, (uint64_t)0);
+    v += dpp_val<kDppRowShr8, 0xf>(v, (uint64_t)0);
+    // lane 16 r + 15 holds the sum of row r
+    return read_uniform_lane(v, 15) + read_uniform_lane(v, 31) + read_uniform_lane(v, 47) + read_uniform_lane(v, 63);
+}
+
+// Records of each class in every chunk of the flat map, from the points'
+// closed-form class counts (the emitter's chunks, without producing them):
+// cnt[c] in packed 16-bit fields (a chunk holds at most 2^16 - 1 records),
+// which must start at zero.  One thread per point; a point's records in the
+// chunk of its first record are summed over the lanes that share that chunk
+// (consecutive points, so a wavefront spans few chunks) and added with one
+// atomic; the rare points whose records run into later chunks add those
+// parts one by one.
+constexpr int kChunkGroup = 1024;  // chunks per group of the offset sums
+
+__device__ __forceinline__ void unpack_class_counts(uint64_t v, uint64_t &w01, uint64_t &w23) {
+    w01 = (v & 0xffffull) | (((v >> 16) & 0xffffull) << 32);
+    w23 = ((v >> 32) & 0xffffull) | ((v >> 48) << 32);
+}
+
+template <int NAX>
+__global__ __launch_bounds__(256) void chunk_class_kernel(EmitArgs a, int chunk_shift,
+                                                          unsigned long long *__restrict__ cnt) {
+    const int lane = lane_id();
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    // every lane of a wavefront runs the same number of rounds (wavefront sums below)
+    const uint64_t base0 = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(uint64_t)(kWave - 1));
+    for (uint64_t kb = base0; kb < a.n; kb += stride) {
+        const uint64_t k = kb + lane;
+        const bool valid = k < a.n;
+        uint64_t b = 0, e = 0;
+        uint32_t pay = 0;
+        uint32_t rk[NAX > 0 ? NAX : 1];
+        if (valid) {
+            b = a.off[k];
+            e = a.off[k + 1];
+            pay = a.pay[k];
+#pragma unroll
+            for (int ax = 0; ax < NAX; ++ax) rk[ax] = a.rs[(uint64_t)ax * a.n + k];
+        }
+        const bool has = valid && e > b;
+        const uint64_t c0 = b >> chunk_shift;
+        uint64_t v = 0, end0 = 0;
+        if (has) {
+            end0 = (c0 + 1) << chunk_shift;
+            if (end0 > e) end0 = e;
+            v = point_class_counts<NAX>(a, pay, rk, 0u, (uint32_t)(end0 - b));
+        }
+        // sum over the lanes sharing a first chunk, one atomic per chunk
+        uint64_t todo = __ballot(has);
+        while (todo) {
+            const int leader = __ffsll((unsigned long long)todo) - 1;
+            const uint64_t cl = read_uniform_lane(c0, leader);
+            const uint64_t same = __ballot(has && c0 == cl);
+            const uint64_t sum = wave_sum_u64(((same >> lane) & 1ull) ? v : 0ull);
+            if (lane == leader) atomicAdd(&cnt[cl], (unsigned long long)sum);
+            todo &= ~same;
+        }
+        // records past the first chunk (points straddling chunk ends)
+        if (has && end0 < e) {
+            for (uint64_t lo = end0; lo < e; lo += (1ull << chunk_shift)) {
+                const uint64_t hi = (lo + (1ull << chunk_shift) < e) ? lo + (1ull << chunk_shift) : e;
+                atomicAdd(&cnt[lo >> chunk_shift],
+                          (unsigned long long)point_class_counts<NAX>(a, pay, rk, (uint32_t)(lo - b), (uint32_t)(hi - b)));
+            }
+        }
+    }
+}
+
+// Class sums of each group of kChunkGroup chunks (one workgroup per group):
+// gsum[2 g] holds classes 0 and 1, gsum[2 g + 1] classes 2 and 3, in 32-bit
+// fields (every class has fewer than 2^32 records).
+__global__ __launch_bounds__(256) void chunk_group_kernel(const unsigned long long *__restrict__ cnt, uint64_t nchunks,
+                                                          unsigned long long *__restrict__ gsum) {
+    constexpr int BLOCK = 256;
+    __shared__ uint64_t s_tmp[BLOCK / kWave];
+    const uint64_t c0 = (uint64_t)blockIdx.x * kChunkGroup;
+    uint64_t s01 = 0, s23 = 0;
+#pragma unroll
+    for (int i = 0; i < kChunkGroup / BLOCK; ++i) {
+        const uint64_t c = c0 + (uint64_t)i * BLOCK + threadIdx.x;
+        uint64_t w01 = 0, w23 = 0;
+        if (c < nchunks) unpack_class_counts(cnt[c], w01, w23);
+        s01 += w01;
+        s23 += w23;
+    }
+    uint64_t t01, t23;
+    block_excl_sum_packed<BLOCK>(s01, s_tmp, &t01);
+    block_excl_sum_packed<BLOCK>(s23, s_tmp, &t23);
+    if (threadIdx.x == 0) {
+        gsum[2 * blockIdx.x] = t01;
+        gsum[2 * blockIdx.x + 1] = t23;
+    }
+}
+
+// Exclusive sums of the per-chunk class counts: off[c] = (records of class
+// q in the chunks before c, q = 0..3); tot[q] = all records of class q.
+// One workgroup per group of kChunkGroup chunks (kChunkGroup / 256 chunks
+// per thread); a group's start is the sum of the groups before it.
+__global__ __launch_bounds__(256) void chunk_offsets_kernel(const unsigned long long *__restrict__ cnt,
+                                                            const unsigned long long *__restrict__ gsum,
+                                                            uint64_t nchunks, uint4 *__restrict__ off,
+                                                            unsigned long long *__restrict__ tot) {
+    constexpr int BLOCK = 256, PER = kChunkGroup / BLOCK;
+    __shared__ uint64_t s_tmp[BLOCK / kWave];
+    __shared__ uint64_t s_base[2];
+    const uint64_t g = blockIdx.x;
+    const uint64_t ngroups = (nchunks + kChunkGroup - 1) / kChunkGroup;
+    if (threadIdx.x < kWave) {
+        // groups before this one (and, for group 0, all of them: the totals)
+        const uint64_t upto = g == 0 ? ngroups : g;
+        uint64_t b01 = 0, b23 = 0;
+        for (uint64_t h = threadIdx.x; h < upto; h += kWave) {
+            b01 += gsum[2 * h];
+            b23 += gsum[2 * h + 1];
+        }
+        b01 = wave_sum_u64(b01);
+        b23 = wave_sum_u64(b23);
+        if (threadIdx.x == 0) {
+            if (g == 0) {
+                tot[0] = (uint32_t)b01;
+                tot[1] = b01 >> 32;
+                tot[2] = (uint32_t)b23;
+                tot[3] = b23 >> 32;
+                b01 = b23 = 0;
+            }
+            s_base[0] = b01;
+            s_base[1] = b23;
+        }
+    }
+    const uint64_t c0 = g * kChunkGroup + (uint64_t)threadIdx.x * PER;
+    uint64_t v[PER];
+    uint64_t s01 = 0, s23 = 0;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        v[i] = c0 + i < nchunks ? cnt[c0 + i] : 0ull;
+        uint64_t w01, w23;
+        unpack_class_counts(v[i], w01, w23);
+        s01 += w01;
+        s23 += w23;
+    }
+    uint64_t t01, t23;
+    uint64_t r01 = block_excl_sum_packed<BLOCK>(s01, s_tmp, &t01);  // (plain 64-bit sums: 32-bit fields never carry)
+    uint64_t r23 = block_excl_sum_packed<BLOCK>(s23, s_tmp, &t23);
+    r01 += s_base[0];
+    r23 += s_base[1];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        if (c0 + i < nchunks)
+            off[c0 + i] = make_uint4((uint32_t)r01, (uint32_t)(r01 >> 32), (uint32_t)r23, (uint32_t)(r23 >> 32));
+        uint64_t w01, w23;
+        unpack_class_counts(v[i], w01, w23);
+        r01 += w01;
+        r23 += w23;
+    }
+}
+
+// HIST: the kernel builds the record sort's digit histograms (a.hist_part);
+// without it they come from elsewhere and the LDS for them is not reserved.
+template <class K, int NAX, int BLOCK, int ITEMS, bool CLS, bool HIST = true>
 __global__ __launch_bounds__(BLOCK) void emit_kernel(EmitArgs a, K *__restrict__ keys_a, uint32_t *__restrict__ vals_a,
                                                      K *__restrict__ keys_b, uint32_t *__restrict__ vals_b) {
     constexpr int CHUNK = BLOCK * ITEMS;
     // histogram rows: passes of every class (up to 1+2+3+4 for 32-bit keys)
-    constexpr int kRows = CLS ? (sizeof(K) == 4 ? 10 : 26) : kMaxPasses;
+    constexpr int kRows = !HIST ? 1 : CLS ? (sizeof(K) == 4 ? 10 : 26) : kMaxPasses;
     using PC = PointCache<NAX>;
-    using DW = DigitWord<unsigned long long>;
     __shared__ PC s_pc;
     __shared__ K s_keys[CHUNK];
     __shared__ uint32_t s_pay[CHUNK];
-    __shared__ uint32_t s_hist[kRows * kRadix];
+    __shared__ uint32_t s_hist[HIST ? kRows * kRadix : 1];
     __shared__ unsigned long long s_data;
     __shared__ uint64_t s_scan[BLOCK / kWave];
     __shared__ uint64_t s_cdst[kMaxClasses];  // destination of the chunk's first slot of each class, minus its run start
-    __shared__ uint32_t s_chunk;
-    // (with classes the histograms may come from elsewhere: hist_part null)
-    const int rows = a.hist_part ? (CLS ? a.hist_rows : a.passes) : 0;
+    __shared__ uint32_t s_next[2];            // the block's next chunk's point range
+    __shared__ uint16_t s_tfirst[BLOCK];      // cached chunks: the point holding each thread's first record (< kCap)
+    const int rows = (HIST && a.hist_part) ? (CLS ? a.hist_rows : a.passes) : 0;
     for (int i = threadIdx.x; i < rows * kRadix; i += BLOCK) s_hist[i] = 0;
     if (threadIdx.x == 0) s_data = 0;
     uint32_t my_data = 0;
@@ -763,186 +908,248 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(EmitArgs a, K *__restrict__
 
     // the key without the query flag of records that carry weights
     const K kmask = a.flag_shift >= 0 ? ~(K(1) << a.flag_shift) : ~K(0);
+    // one instance: the levels of every axis, read once
+    uint32_t lsingle = ~0u;
+    if (!with_inst) {
+        lsingle = 0;
+#pragma unroll
+        for (int ax = 0; ax < NAX; ++ax) lsingle |= (uint32_t)a.ltab[ax] << (8 * ax);
+    }
+    // class region starts
+    __shared__ uint64_t s_cls_base[kMaxClasses];
+    if (threadIdx.x < kMaxClasses) s_cls_base[threadIdx.x] = a.cls_base[threadIdx.x];
 
     const uint64_t nchunks = (a.E + CHUNK - 1) / CHUNK;
-    for (;;) {
-        __syncthreads();  // previous chunk done with LDS
-        if (threadIdx.x == 0) s_chunk = atomicAdd(a.ticket, 1u);
-        __syncthreads();
-        const uint64_t c = s_chunk;
-        if (c >= nchunks) break;
+    // Block b takes chunks b, b + G, b + 2G, ... (G = gridDim.x; every chunk
+    // holds CHUNK records and its class offsets are precomputed, so there is
+    // no ordering between chunks).  The state of a chunk's points is loaded
+    // into registers while the previous chunk's records are stored, and
+    // moved into LDS when the chunk starts; a chunk whose points do not fit
+    // the cache reads them from global memory during its walk.
+    constexpr uint32_t kCap = PC::kCap;
+    static_assert(kCap <= 2 * BLOCK, "at most two point slots per thread");
+    const uint32_t *off_lo = reinterpret_cast<const uint32_t *>(a.off);  // low words: offsets within a chunk fit 32 bits
+    const uint32_t i0 = threadIdx.x, i1 = threadIdx.x + BLOCK, i2 = threadIdx.x + 2 * BLOCK;
+    // the prefetched state (slots i0, i1; offsets also at i2 and i0 + 1,
+    // i1 + 1) and class offset
+    uint32_t pf0 = 0, pf1 = 0, pf2 = 0, pg0 = 0, pg1 = 0, py0 = 0, py1 = 0, pw0 = 0, pw1 = 0, pn0 = 0, pn1 = 0;
+    uint32_t pcoff = 0;
+    uint32_t pr0[NAX > 0 ? NAX : 1], pr1[NAX > 0 ? NAX : 1];
+#pragma unroll
+    for (int ax = 0; ax < (NAX > 0 ? NAX : 1); ++ax) pr0[ax] = pr1[ax] = 0;
+    // point range [klo, khi] of chunk c (khi < n: the point holding the next
+    // chunk's first record, or the last point)
+    auto chunk_lo = [&](uint64_t c) -> uint32_t { return a.chunk_k[c]; };
+    auto chunk_hi = [&](uint64_t c) -> uint32_t { return (c + 1 < nchunks) ? a.chunk_k[c + 1] : a.n - 1; };
+    auto prefetch = [&](uint64_t c, uint32_t klo, uint32_t khi) {
+        if constexpr (CLS) pcoff = a.cls_off[c * kMaxClasses + (threadIdx.x & (kMaxClasses - 1))];
+        const uint32_t npts = khi - klo + 1;
+        if (npts > kCap) return;
+        // clamped indices: every load in bounds (klo + npts <= n), only the LDS stores are predicated
+        const uint32_t j0 = i0 < npts ? i0 : npts - 1, j1 = i1 < npts ? i1 : npts - 1;
+        pf0 = off_lo[2ull * (klo + (i0 <= npts ? i0 : npts))];
+        pf1 = off_lo[2ull * (klo + (i1 <= npts ? i1 : npts))];
+        pf2 = off_lo[2ull * (klo + (i2 <= npts ? i2 : npts))];
+        pg0 = off_lo[2ull * (klo + (i0 + 1 <= npts ? i0 + 1 : npts))];  // the ends of points i0, i1
+        pg1 = off_lo[2ull * (klo + (i1 + 1 <= npts ? i1 + 1 : npts))];
+        py0 = a.pay[klo + j0];
+        py1 = a.pay[klo + j1];
+        if (a.wv) {
+            pw0 = a.wv[klo + j0];
+            pw1 = a.wv[klo + j1];
+        }
+        if (with_inst) {
+            pn0 = a.inst_s[klo + j0];
+            pn1 = a.inst_s[klo + j1];
+        }
+#pragma unroll
+        for (int ax = 0; ax < NAX; ++ax) {
+            pr0[ax] = a.rs[(uint64_t)ax * a.n + klo + j0];
+            pr1[ax] = a.rs[(uint64_t)ax * a.n + klo + j1];
+        }
+    };
+    uint64_t c = blockIdx.x;
+    uint32_t klo = 0, khi = 0;
+    if (c < nchunks) {
+        klo = chunk_lo(c);
+        khi = chunk_hi(c);
+        prefetch(c, klo, khi);
+    }
+    for (; c < nchunks; c += gridDim.x) {
+        const uint64_t cn = c + gridDim.x;
         const uint64_t o0 = c * CHUNK;
         const uint64_t o1 = (o0 + CHUNK < a.E) ? o0 + CHUNK : a.E;
-        const uint32_t klo = a.chunk_k[c];
-        const uint32_t khi = (c + 1 < nchunks) ? a.chunk_k[c + 1] : a.n - 1;  // may be one past
         const uint32_t npts = khi - klo + 1;
-        const bool cached = npts <= (uint32_t)PC::kCap;
-        const uint64_t obase = a.off[klo];
-        if (cached) {
-            for (uint32_t i = threadIdx.x; i <= npts; i += BLOCK) s_pc.off[i] = (uint32_t)(a.off[klo + i] - obase);
-            for (uint32_t i = threadIdx.x; i < npts; i += BLOCK) {
-                s_pc.pay[i] = a.pay[klo + i];
-                s_pc.wv[i] = a.wv ? a.wv[klo + i] : 0u;
-                s_pc.inst[i] = with_inst ? a.inst_s[klo + i] : 0u;
-#pragma unroll
-                for (int ax = 0; ax < NAX; ++ax) s_pc.rank[ax][i] = a.rs[(uint64_t)ax * a.n + klo + i];
-            }
-        }
-        __syncthreads();
-        auto offr = [&](uint32_t i) -> uint32_t {
-            return cached ? s_pc.off[i] : (uint32_t)(a.off[klo + i] - obase);
-        };
         const uint32_t nrec = (uint32_t)(o1 - o0);
-
-        const uint64_t r0 = o0 + (uint64_t)threadIdx.x * ITEMS;
-        PointWalk<NAX> pw;
-        uint32_t idx = 0, left = 0;
-        if (r0 < o1) {
-            const uint32_t rel = (uint32_t)(r0 - obase);
-            uint32_t lo = 0, hi = npts;  // offr(lo) <= rel < offr(hi)
-            while (hi - lo > 1) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (offr(mid) <= rel) lo = mid; else hi = mid;
+        uint32_t nklo = 0, nkhi = 0;
+        uint64_t tot = 0;  // the chunk's records per class (packed)
+        // one copy of the chunk's code for cached and one for uncached points
+        // (a run-time choice inside the loops below would make every wait
+        // for LDS also wait for global memory)
+        auto chunk = [&](auto cached_c) {
+            constexpr bool cached = decltype(cached_c)::value;
+            if (cached) {
+                // (the previous chunk's walk is over: its last barrier came after it)
+                if (i0 <= npts) s_pc.off[i0] = pf0;
+                if (i1 <= npts) s_pc.off[i1] = pf1;
+                if (i2 <= npts) s_pc.off[i2] = pf2;
+                if (i0 < npts) {
+                    s_pc.pay[i0] = py0;
+                    s_pc.wv[i0] = pw0;
+                    s_pc.inst[i0] = pn0;
+#pragma unroll
+                    for (int ax = 0; ax < NAX; ++ax) s_pc.rank[ax][i0] = pr0[ax];
+                }
+                if (i1 < npts) {
+                    s_pc.pay[i1] = py1;
+                    s_pc.wv[i1] = pw1;
+                    s_pc.inst[i1] = pn1;
+#pragma unroll
+                    for (int ax = 0; ax < NAX; ++ax) s_pc.rank[ax][i1] = pr1[ax];
+                }
+                // each point marks the threads whose first record (o0 + ITEMS t)
+                // it holds: records [fs, fe), low words, taken relative to o0
+                auto mark = [&](uint32_t i, uint32_t fs, uint32_t fe) {
+                    const int32_t ds = (int32_t)(fs - (uint32_t)o0), de = (int32_t)(fe - (uint32_t)o0);
+                    const int32_t tlo = ds <= 0 ? 0 : (ds + ITEMS - 1) / ITEMS;
+                    int32_t thi = de <= 0 ? 0 : (de + ITEMS - 1) / ITEMS;
+                    if (thi > BLOCK) thi = BLOCK;
+                    for (int32_t t = tlo; t < thi; ++t) s_tfirst[t] = (uint16_t)i;
+                };
+                if (i0 < npts) mark(i0, pf0, pg0);
+                if (i1 < npts) mark(i1, pf1, pg1);
             }
-            idx = lo;
-            pw.load(a, &s_pc, cached, klo, idx);
-            const uint32_t t = rel - offr(idx);
-            left = offr(idx + 1) - offr(idx) - t;  // records left in this point
-            pw.seek(t);
-        }
+            // (thread q < classes) records of class q in the chunks before this one
+            const uint32_t coff = pcoff;
+            __syncthreads();  // point cache written; every thread done with the previous chunk's staging
+            // (the uncached reads are 64-bit: a select between the LDS and the
+            // global address would make one flat load, which waits on both)
+            const uint32_t obase = cached ? s_pc.off[0] : (uint32_t)a.off[klo];
+            auto offr = [&](uint32_t i) -> uint32_t {
+                return (cached ? s_pc.off[i] : (uint32_t)a.off[klo + i]) - obase;
+            };
 
-        // With classes: this thread's records per class, from its points
-        // (before they are produced), scanned over the block.  That gives
-        // each record's slot in the class-split staging and the chunk's
-        // counts, which are published at once so that later chunks can look
-        // past this one while its records are still being produced.
-        uint64_t mine = 0, tot = 0, expect = 0;
-        if constexpr (CLS) {
+            const uint64_t r0 = o0 + (uint64_t)threadIdx.x * ITEMS;
+            PointWalk<NAX> pw;
+            uint32_t idx = 0, left = 0;
             if (r0 < o1) {
-                uint32_t need = (uint32_t)((o1 - r0) < (uint64_t)ITEMS ? (o1 - r0) : (uint64_t)ITEMS);
-                uint32_t k = idx, ta = offr(idx + 1) - offr(idx) - left;
-                while (need) {
-                    const uint32_t pcnt = offr(k + 1) - offr(k);
-                    const uint32_t tb = (pcnt - ta < need) ? pcnt : ta + need;
-                    if (tb > ta) {
-                        uint32_t rk[NAX > 0 ? NAX : 1];
-                        uint32_t pay;
-                        if (cached) {
-                            pay = s_pc.pay[k];
-#pragma unroll
-                            for (int ax = 0; ax < NAX; ++ax) rk[ax] = s_pc.rank[ax][k];
-                        } else {
-                            pay = a.pay[klo + k];
-#pragma unroll
-                            for (int ax = 0; ax < NAX; ++ax) rk[ax] = a.rs[(uint64_t)ax * a.n + klo + k];
-                        }
-                        expect += point_class_counts<NAX>(a, pay, rk, ta, tb);
-                        need -= tb - ta;
+                const uint32_t rel = (uint32_t)r0 - obase;
+                if (cached) {
+                    idx = s_tfirst[threadIdx.x];
+                } else {
+                    uint32_t lo = 0, hi = npts;  // offr(lo) <= rel < offr(hi)
+                    while (hi - lo > 1) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (offr(mid) <= rel) lo = mid; else hi = mid;
                     }
-                    ++k;
-                    ta = 0;
+                    idx = lo;
                 }
+                pw.load(a, &s_pc, cached, klo, idx, lsingle);
+                const uint32_t t = rel - offr(idx);
+                left = offr(idx + 1) - offr(idx) - t;  // records left in this point
+                pw.seek(t);
             }
-            mine = block_excl_sum_packed<BLOCK>(expect, s_scan, &tot);
-            if (threadIdx.x < (unsigned)a.ncls) {
-                const int q = threadIdx.x;
-                store_agent(&a.cls_status[c * kMaxClasses + q],
-                            DW::make(c == 0 ? kFlagInclusive : kFlagAggregate, (uint32_t)(tot >> (16 * q)) & 0xffffu));
-            }
-        }
 
-        uint64_t seen = 0;  // records produced per class (checked against the expectation)
+            // With classes: this thread's records per class, from its points
+            // (before they are produced), scanned over the block.  That gives
+            // each record's slot in the class-split staging and the chunk's
+            // counts per class.
+            uint64_t mine = 0, expect = 0;
+            if constexpr (CLS) {
+                if (r0 < o1) {
+                    uint32_t need = (uint32_t)((o1 - r0) < (uint64_t)ITEMS ? (o1 - r0) : (uint64_t)ITEMS);
+                    uint32_t k = idx, ta = offr(idx + 1) - offr(idx) - left;
+                    while (need) {
+                        const uint32_t pcnt = offr(k + 1) - offr(k);
+                        const uint32_t tb = (pcnt - ta < need) ? pcnt : ta + need;
+                        if (tb > ta) {
+                            uint32_t rk[NAX > 0 ? NAX : 1];
+                            uint32_t pay;
+                            if (cached) {
+                                pay = s_pc.pay[k];
+#pragma unroll
+                                for (int ax = 0; ax < NAX; ++ax) rk[ax] = s_pc.rank[ax][k];
+                            } else {
+                                pay = a.pay[klo + k];
+#pragma unroll
+                                for (int ax = 0; ax < NAX; ++ax) rk[ax] = a.rs[(uint64_t)ax * a.n + klo + k];
+                            }
+                            expect += point_class_counts<NAX>(a, pay, rk, ta, tb);
+                            need -= tb - ta;
+                        }
+                        ++k;
+                        ta = 0;
+                    }
+                }
+                mine = block_excl_sum_packed<BLOCK>(expect, s_scan, &tot);
+                // destination of the chunk's first staged record of each class,
+                // minus its staging position
+                if (threadIdx.x < (unsigned)a.ncls) {
+                    const int q = threadIdx.x;
+                    s_cdst[q] = s_cls_base[q] + coff - packed_prefix(tot, q);
+                }
+            }
+
+            // (thread 0) the next chunk's point range: loaded now, passed on
+            // through LDS once this chunk's records are produced
+            uint32_t tlo = 0, thi = 0;
+            if (threadIdx.x == 0 && cn < nchunks) {
+                tlo = chunk_lo(cn);
+                thi = chunk_hi(cn);
+            }
+            uint64_t seen = 0;  // records produced per class (checked against the expectation)
 #pragma unroll 1
-        for (int j = 0; j < ITEMS; ++j) {
-            const bool valid = r0 + j < o1;
-            K key = 0;
-            if (valid) {
-                key = pw.template key<K>(a.inst_shift, with_inst, a.field_shift, a.flag_shift);
-                uint32_t lp = threadIdx.x * ITEMS + j;
-                if constexpr (CLS) {
-                    const int q = key_class(key & kmask, a.cls_c0);
-                    lp = packed_prefix(tot, q) + ((uint32_t)(mine >> (16 * q)) & 0xffffu);
-                    mine += 1ull << (16 * q);
-                    seen += 1ull << (16 * q);
+            for (int j = 0; j < ITEMS; ++j) {
+                const bool valid = r0 + j < o1;
+                K key = 0;
+                if (valid) {
+                    key = pw.template key<K>(a.inst_shift, with_inst, a.field_shift, a.flag_shift);
+                    uint32_t lp = threadIdx.x * ITEMS + j;
+                    if constexpr (CLS) {
+                        const int q = key_class(key & kmask, a.cls_c0);
+                        lp = packed_prefix(tot, q) + ((uint32_t)(mine >> (16 * q)) & 0xffffu);
+                        mine += 1ull << (16 * q);
+                        seen += 1ull << (16 * q);
+                    }
+                    if (lp < (uint32_t)CHUNK) {
+                        s_keys[lp] = key;
+                        s_pay[lp] = pw.payload;
+                    }
+                    my_data += pw.isq ? 0u : 1u;
+                    if (--left) {
+                        pw.next();
+                    } else if (r0 + j + 1 < o1) {
+                        // next point with records (points without records have equal offsets)
+                        do {
+                            ++idx;
+                            left = offr(idx + 1) - offr(idx);
+                        } while (left == 0);
+                        pw.load(a, &s_pc, cached, klo, idx, lsingle);
+                    }
                 }
-                if (lp < (uint32_t)CHUNK) {
-                    s_keys[lp] = key;
-                    s_pay[lp] = pw.payload;
-                }
-                my_data += pw.isq ? 0u : 1u;
-                if (--left) {
-                    pw.next();
-                } else if (r0 + j + 1 < o1) {
-                    // next point with records (points without records have equal offsets)
-                    do {
-                        ++idx;
-                        left = offr(idx + 1) - offr(idx);
-                    } while (left == 0);
-                    pw.load(a, &s_pc, cached, klo, idx);
+                if constexpr (!CLS) {
+                    if (rows) hist_add(s_hist, key, valid, a.passes, peel_from);
+                } else {
+                    const int q = valid ? key_class(key & kmask, a.cls_c0) : 0;
+                    const uint32_t ci = (uint32_t)(cls_info >> (16 * q));
+                    if (rows) hist_add_rows(s_hist, key, valid, (int)(ci & 0xffu), (int)((ci >> 8) & 0xffu), a.passes);
                 }
             }
-            if constexpr (!CLS) {
-                if (rows) hist_add(s_hist, key, valid, a.passes, peel_from);
-            } else {
-                const int q = valid ? key_class(key & kmask, a.cls_c0) : 0;
-                const uint32_t ci = (uint32_t)(cls_info >> (16 * q));
-                if (rows) hist_add_rows(s_hist, key, valid, (int)(ci & 0xffu), (int)((ci >> 8) & 0xffu), a.passes);
+            if constexpr (CLS) {
+                if (seen != expect) atomicOr(a.error, 1u);  // records disagree with the class counts: reported
             }
-        }
-        if constexpr (CLS) {
-            if (seen != expect) atomicOr(a.error, 1u);  // records disagree with the class counts: reported
-            // Class offsets from the chunks before this one, by wavefront 0
-            // after its share of the records (by then the chunks before have
-            // mostly published inclusive words): lane 16 q + k reads chunk
-            // hi - k for class q, 16 chunks per class per round trip; a
-            // class's walk ends at the nearest inclusive word (chunk 0
-            // publishes one at once).
-            if (threadIdx.x < kWave) {
-                const int lane = threadIdx.x, q = lane >> 4, k = lane & 15;
-                const bool act = q < a.ncls;
-                const uint32_t count = act ? ((uint32_t)(tot >> (16 * q)) & 0xffffu) : 0u;
-                unsigned long long *st = a.cls_status;
-                uint64_t excl = 0;
-                bool done = !act || c == 0;
-                int64_t hi = (int64_t)c - 1;
-                constexpr int kDepth = 4;  // chunks per lane and round trip (loads issued together)
-                while (__ballot(!done)) {
-                    unsigned long long w[kDepth];
-#pragma unroll
-                    for (int d = 0; d < kDepth; ++d) {
-                        const int64_t t = hi - k - 16 * d;
-                        w[d] = (!done && t >= 0) ? load_agent(&st[(uint64_t)t * kMaxClasses + q]) : DW::make(1, 0);
-                    }
-#pragma unroll
-                    for (int d = 0; d < kDepth; ++d) {
-                        const int64_t t = hi - k - 16 * d;
-                        while (DW::flag(w[d]) == 0) {
-                            __builtin_amdgcn_s_sleep(2);
-                            w[d] = load_agent(&st[(uint64_t)t * kMaxClasses + q]);
-                        }
-                    }
-#pragma unroll
-                    for (int d = 0; d < kDepth; ++d) {
-                        const int64_t t = hi - k - 16 * d;
-                        const uint64_t im = __ballot(!done && t >= 0 && DW::flag(w[d]) == kFlagInclusive);
-                        const uint32_t gm = (uint32_t)(im >> (16 * q)) & 0xffffu;
-                        const int k0 = gm ? __ffs(gm) - 1 : 15;  // nearest inclusive chunk of the class
-                        const uint64_t v =
-                            row_sum_u64((!done && t >= 0 && k <= k0) ? (uint64_t)(w[d] & DW::kMask) : 0ull);
-                        if (!done) {
-                            excl += v;
-                            done = gm != 0;
-                        }
-                    }
-                    hi -= 16 * kDepth;
-                }
-                if (act && k == 0) {
-                    if (c > 0) store_agent(&st[c * kMaxClasses + q], DW::make(kFlagInclusive, excl + count));
-                    s_cdst[q] = a.cls_base[q] + excl - packed_prefix(tot, q);
-                }
+            if (threadIdx.x == 0) {
+                s_next[0] = tlo;
+                s_next[1] = thi;
             }
-        }
-        __syncthreads();
+        };
+        if (npts <= kCap) chunk(std::true_type{});
+        else chunk(std::false_type{});
+        __syncthreads();  // staging complete
+        nklo = s_next[0];
+        nkhi = s_next[1];
+        // the next chunk's points, loaded while this chunk's records are stored
+        if (cn < nchunks) prefetch(cn, nklo, nkhi);
         if constexpr (!CLS) {
             for (uint32_t i = threadIdx.x; i < nrec; i += BLOCK) {
                 keys_a[o0 + i] = s_keys[i];
@@ -965,6 +1172,8 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(EmitArgs a, K *__restrict__
                 }
             }
         }
+        klo = nklo;
+        khi = nkhi;
     }
     __syncthreads();
     if (rows) hist_flush(s_hist, a.hist_part, rows);

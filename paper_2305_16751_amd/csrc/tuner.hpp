@@ -19,7 +19,7 @@ namespace domagg {
 
 struct TuneChoice {
     int record_sort_tile = 4096;  // onesweep tile: 2048 (256 x 8), 4096 (256 x 16), 8192 (512 x 16) or 16384 (512 x 32)
-    int point_sort_tile = 4096;
+    int point_sort_tile = 8192;
     int scan_items = 16;          // segmented-scan tile = 256 * items (8 forced for 64-bit keys)
 };
 
