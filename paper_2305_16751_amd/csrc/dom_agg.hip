@@ -610,13 +610,15 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
             rp.cdf_q = P->cdf_q.as<uint32_t>();
             rp.dinv = P->dinv.as<uint32_t>();
             rp.qinv = P->qinv.as<uint32_t>();
-            scan_launch<RankProblem<KP, true>, sizeof(KP) == 4 ? 16 : 8>(
+            // (2048-element tiles: the rank scan's scattered per-point
+            // stores want more resident tiles than its loads want long ones)
+            scan_launch<RankProblem<KP, true>, 8>(
                 "rank_scan", rp, n, scan_status.as<uint64_t>(), scan_status.bytes / 8,
                 scan_ticket.as<uint32_t>(), s);
         } else if (axis < nax) {
             RankProblem<KP> rp{sk.as<KP>(), sv.as<uint32_t>(), rank.as<uint32_t>() + (size_t)axis * n,
                                kcount.as<uint32_t>() + (size_t)axis * ni, n, (uint32_t)ni};
-            scan_launch<RankProblem<KP>, sizeof(KP) == 4 ? 16 : 8>(
+            scan_launch<RankProblem<KP>, 8>(
                 "rank_scan", rp, n, scan_status.as<uint64_t>(), scan_status.bytes / 8,
                 scan_ticket.as<uint32_t>(), s);
         } else {
