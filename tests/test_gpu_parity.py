@@ -299,3 +299,40 @@ def test_small_batch_with_empty_instances(m):
         if Dk.shape[0]:
             want = oracle.transposed_sum(m, Dk, Qk, g[qoff[k]:qoff[k + 1]])
             np.testing.assert_allclose(gw[doff[k]:doff[k + 1]], want, rtol=1e-12, atol=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# the flat map's uncached chunks
+
+
+def test_flat_map_chunks_spanning_many_points():
+    """Points that yield at most one record each: data at first-axis ranks
+    with at most one 0 digit, queries at ranks with at most one 1 digit
+    (Lemma 2's prefix sets, L = 10, every rank present once more so that
+    K = 2^10).  A 2048-record chunk then spans more points than the flat map
+    caches, so its walk reads them from global memory; the 10-bit node keys
+    still split the sort into two classes."""
+    from paper_2305_16751_amd import dom_agg_run
+    rng = np.random.default_rng(2305)
+    L = 10
+    K = 1 << L
+    dvals = np.array([K - 1] + [(K - 1) ^ (1 << b) for b in range(L)])
+    qvals = np.array([0] + [1 << b for b in range(L)])
+    nb = 30000
+    d0 = np.concatenate([np.arange(K), rng.choice(dvals, nb)])
+    q0 = np.concatenate([np.arange(K), rng.choice(qvals, nb)])
+    D = np.stack([d0, rng.integers(0, 1 << 20, d0.size)], 1).astype(np.int32)
+    Q = np.stack([q0, rng.integers(0, 1 << 20, q0.size)], 1).astype(np.int32)
+    w = rng.integers(-1000, 1000, size=D.shape[0]).astype(np.int64)
+    c = workloads.Case("many_points_per_chunk", 2, D, Q, w)
+    p, _ = _run_and_check(c, "sum", np.int64)
+    info = p.info()
+    assert info["sort_classes"] >= 2, info
+    # at most one record per bulk point: well under 480 points' worth per chunk
+    assert info["records"] < 2 * (nb + K * L), info
+    # the one-shot entry point (records carrying 4-byte weights)
+    w32 = w.astype(np.float32)
+    got = dom_agg_run(to_dev(D), to_dev(Q), to_dev(w32), "sum")
+    want = oracle.construction(2, D, Q, w32.astype(np.float64), "sum")
+    scale = oracle.construction(2, D, Q, np.abs(w32.astype(np.float64)), "sum")
+    check_fp(got, want, scale, "one-shot, many points per chunk")
