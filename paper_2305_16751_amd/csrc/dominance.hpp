@@ -62,7 +62,9 @@ __global__ __launch_bounds__(BLOCK) void extract_keys_kernel(
             keys[s] = key;
             vals[s] = ppos ? ppos[s] : (uint32_t)s;
         }
-        hist_add(s_hist, key, valid, passes);
+        // (the low digits of coordinate keys are spread; the top one, with
+        // the sign and exponent, and the instance digits are skewed)
+        hist_add(s_hist, key, valid, passes, sizeof(K) == 8 ? 3 : passes - 1);
     }
     if (saw_nan) atomicOr(nan_flag, 1u);
     __syncthreads();
@@ -114,7 +116,9 @@ __global__ __launch_bounds__(BLOCK) void extract_sigma_kernel(
             keys[s] = key;
             vals[s] = ((uint64_t)((isq ? 0x80000000u : 0u) | r) << 32) | payload;
         }
-        hist_add(s_hist, key, valid, passes);
+        // (the low digits of coordinate keys are spread; the top one, with
+        // the sign and exponent, and the instance digits are skewed)
+        hist_add(s_hist, key, valid, passes, sizeof(K) == 8 ? 3 : passes - 1);
     }
     if (saw_nan) atomicOr(nan_flag, 1u);
     __syncthreads();
