@@ -54,11 +54,21 @@ __global__ __launch_bounds__(BLOCK) void seg_scan_kernel(P p, uint64_t n,
     // status: [tiles] inclusive-or-aggregate words, then [tiles] aggregate words
     uint64_t *const aggs = status + ((n + TILE - 1) / TILE) * ScanStatusWords<V>::kWords;
 
+    {
+        // every load of the tile in flight before the first LDS store: the
+        // indices are clamped into [0, n), so no load is predicated (a
+        // predicated load followed by its store waited once per item)
+        Raw rr[ITEMS];
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-        const int li = j * BLOCK + tid;
-        const uint64_t i = base + li;
-        if (i < n) s_raw[pidx(li)] = p.load(i);
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint64_t i = base + (uint64_t)j * BLOCK + tid;
+            rr[j] = p.load(i < n ? i : n - 1);
+        }
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const int li = j * BLOCK + tid;
+            if (base + li < n) s_raw[pidx(li)] = rr[j];
+        }
     }
     if (tid == 0 && base > 0) s_pred = p.load(base - 1);
     if (tid == BLOCK - 1 && base + TILE < n) s_succ = p.load(base + TILE);
