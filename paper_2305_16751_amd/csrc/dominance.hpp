@@ -1388,8 +1388,21 @@ __global__ __launch_bounds__(256) void regroup_kernel(RegroupArgs a, const V *__
         if constexpr (NAX == 0) {
             acc = part[o];
         } else if constexpr (NAX == 1) {
-            for (uint32_t j = 0; j < a.radix[0]; ++j)
-                if (ok(0, j)) acc = Monoid<V, OP>::combine(acc, part[(uint64_t)j * a.nout + o]);
+            // 8 slots per round, loaded before any is folded (row indices
+            // clamped below radix), folded in slot order as above
+            constexpr uint32_t kU = 8;
+            const uint32_t R = a.radix[0];
+            for (uint32_t j0 = 0; j0 < R; j0 += kU) {
+                V v[kU];
+#pragma unroll
+                for (uint32_t u = 0; u < kU; ++u) {
+                    const uint32_t j = (j0 + u < R) ? j0 + u : R - 1;
+                    v[u] = part[(uint64_t)j * a.nout + o];
+                }
+#pragma unroll
+                for (uint32_t u = 0; u < kU; ++u)
+                    if (j0 + u < R && ok(0, j0 + u)) acc = Monoid<V, OP>::combine(acc, v[u]);
+            }
         } else if constexpr (NAX == 2) {
             for (uint32_t j0 = 0; j0 < a.radix[0]; ++j0) {
                 const bool v0 = ok(0, j0);
