@@ -47,24 +47,38 @@ __global__ __launch_bounds__(BLOCK) void extract_keys_kernel(
     for (int i = threadIdx.x; i < passes * kRadix; i += BLOCK) s_hist[i] = 0;
     __syncthreads();
     bool saw_nan = false;
-    const uint64_t stride = (uint64_t)gridDim.x * BLOCK;
-    for (uint64_t b = (uint64_t)blockIdx.x * BLOCK; b < n; b += stride) {
-        const uint64_t s = b + threadIdx.x;
-        const bool valid = s < n;
-        K key = 0;
-        if (valid) {
-            const C x = (s < nQ) ? q[s * m + axis] : d[(s - nQ) * m + axis];
-            saw_nan |= is_nan(x);
-            key = (K)ordered_key(x);
-            if constexpr (sizeof(K) == 8) {
-                if (inst_of_slot) key |= (K)inst_of_slot[s] << 32;
-            }
-            keys[s] = key;
-            vals[s] = ppos ? ppos[s] : (uint32_t)s;
+    // U points per thread and round, every load issued before the first is
+    // used (indices clamped below n)
+    constexpr int U = 4;
+    const uint64_t stride = (uint64_t)gridDim.x * BLOCK * U;
+    for (uint64_t b = (uint64_t)blockIdx.x * BLOCK * U; b < n; b += stride) {
+        C xs[U];
+        uint32_t ps[U], is[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t s0 = b + (uint64_t)u * BLOCK + threadIdx.x;
+            const uint64_t s = s0 < n ? s0 : (uint64_t)n - 1;
+            xs[u] = (s < nQ) ? q[s * m + axis] : d[(s - nQ) * m + axis];
+            ps[u] = ppos ? ppos[s] : (uint32_t)s;
+            is[u] = (sizeof(K) == 8 && inst_of_slot) ? inst_of_slot[s] : 0u;
         }
-        // (the low digits of coordinate keys are spread; the top one, with
-        // the sign and exponent, and the instance digits are skewed)
-        hist_add(s_hist, key, valid, passes, sizeof(K) == 8 ? 3 : passes - 1);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t s = b + (uint64_t)u * BLOCK + threadIdx.x;
+            const bool valid = s < n;
+            K key = 0;
+            if (valid) {
+                const C x = xs[u];
+                saw_nan |= is_nan(x);
+                key = (K)ordered_key(x);
+                if constexpr (sizeof(K) == 8) key |= (K)is[u] << 32;
+                keys[s] = key;
+                vals[s] = ps[u];
+            }
+            // (the low digits of coordinate keys are spread; the top one, with
+            // the sign and exponent, and the instance digits are skewed)
+            hist_add(s_hist, key, valid, passes, sizeof(K) == 8 ? 3 : passes - 1);
+        }
     }
     if (saw_nan) atomicOr(nan_flag, 1u);
     __syncthreads();
@@ -89,36 +103,53 @@ __global__ __launch_bounds__(BLOCK) void extract_sigma_kernel(
     for (int i = threadIdx.x; i < passes * kRadix; i += BLOCK) s_hist[i] = 0;
     __syncthreads();
     bool saw_nan = false;
-    const uint64_t stride = (uint64_t)gridDim.x * BLOCK;
-    for (uint64_t b = (uint64_t)blockIdx.x * BLOCK; b < n; b += stride) {
-        const uint64_t s = b + threadIdx.x;
-        const bool valid = s < n;
-        K key = 0;
-        if (valid) {
-            const bool isq = s < nQ;
-            const C x = isq ? q[s * 2 + axis] : d[(s - nQ) * 2 + axis];
-            saw_nan |= is_nan(x);
-            key = (K)ordered_key(x);
-            if constexpr (sizeof(K) == 8) {
-                if (inst_of_slot) key |= (K)inst_of_slot[s] << 32;
-            }
-            const uint64_t rs = pr[s];
-            const uint32_t sp = (uint32_t)rs, r = (uint32_t)(rs >> 32);
-            uint32_t payload;
-            if (isq) {
-                payload = carry_weights ? sp : (kQueryFlag | sp);
-            } else if (carry_weights) {
-                payload = 0;
-                if (w) __builtin_memcpy(&payload, &w[s - nQ], 4);
-            } else {
-                payload = sp - nQ;
-            }
-            keys[s] = key;
-            vals[s] = ((uint64_t)((isq ? 0x80000000u : 0u) | r) << 32) | payload;
+    // U points per thread and round, every load issued before the first is
+    // used (indices clamped below n)
+    constexpr int U = 4;
+    const uint64_t stride = (uint64_t)gridDim.x * BLOCK * U;
+    for (uint64_t b = (uint64_t)blockIdx.x * BLOCK * U; b < n; b += stride) {
+        C xs[U];
+        uint64_t rss[U];
+        uint32_t wbs[U], is[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t s0 = b + (uint64_t)u * BLOCK + threadIdx.x;
+            const uint64_t s = s0 < n ? s0 : (uint64_t)n - 1;
+            xs[u] = (s < nQ) ? q[s * 2 + axis] : d[(s - nQ) * 2 + axis];
+            rss[u] = pr[s];
+            // (weights exist only with data: n > nQ, so the clamped index is in bounds)
+            wbs[u] = 0;
+            if (carry_weights && w && n > nQ) __builtin_memcpy(&wbs[u], &w[s >= nQ ? s - nQ : 0], 4);
+            is[u] = (sizeof(K) == 8 && inst_of_slot) ? inst_of_slot[s] : 0u;
         }
-        // (the low digits of coordinate keys are spread; the top one, with
-        // the sign and exponent, and the instance digits are skewed)
-        hist_add(s_hist, key, valid, passes, sizeof(K) == 8 ? 3 : passes - 1);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t s = b + (uint64_t)u * BLOCK + threadIdx.x;
+            const bool valid = s < n;
+            K key = 0;
+            if (valid) {
+                const bool isq = s < nQ;
+                const C x = xs[u];
+                saw_nan |= is_nan(x);
+                key = (K)ordered_key(x);
+                if constexpr (sizeof(K) == 8) key |= (K)is[u] << 32;
+                const uint64_t rs = rss[u];
+                const uint32_t sp = (uint32_t)rs, r = (uint32_t)(rs >> 32);
+                uint32_t payload;
+                if (isq) {
+                    payload = carry_weights ? sp : (kQueryFlag | sp);
+                } else if (carry_weights) {
+                    payload = wbs[u];
+                } else {
+                    payload = sp - nQ;
+                }
+                keys[s] = key;
+                vals[s] = ((uint64_t)((isq ? 0x80000000u : 0u) | r) << 32) | payload;
+            }
+            // (the low digits of coordinate keys are spread; the top one, with
+            // the sign and exponent, and the instance digits are skewed)
+            hist_add(s_hist, key, valid, passes, sizeof(K) == 8 ? 3 : passes - 1);
+        }
     }
     if (saw_nan) atomicOr(nan_flag, 1u);
     __syncthreads();
