@@ -397,10 +397,9 @@ const char *onesweep_name(int tile) {
 template <class K, class S, int BLOCK, int ITEMS, int ROLE, class VT>
 void onesweep_launch(const K *kin, const VT *vin, K *kout, VT *vout, uint32_t n,
                      int shift, const uint32_t *bases, S *status, uint32_t *ticket, hipStream_t s) {
+    // (status and ticket arrive cleared: one clear serves all passes of a sort)
     constexpr int TILE = BLOCK * ITEMS;
     const unsigned tiles = (unsigned)ceil_div(n, TILE);
-    clear_lookback(reinterpret_cast<uint64_t *>(status), ceil_div((uint64_t)tiles * kRadix * sizeof(S), 8),
-                   ticket, s);
     launch(onesweep_name<K, ROLE>(TILE), s, [&] {
         onesweep_kernel<K, S, BLOCK, ITEMS, ROLE, VT><<<tiles, BLOCK, 0, s>>>(kin, vin, kout, vout, n, shift,
                                                                           bases, status, ticket);
@@ -445,23 +444,32 @@ bool radix_sort(K *kA, VT *vA, K *kB, VT *vB, uint64_t n, const std::vector<int>
     if (n == 0 || shifts.empty()) return false;
     tile = sizeof(VT) == 8 ? 4096 : effective_tile<K, ROLE>(tile);
     const bool narrow = n < (1ull << 30);  // every digit count fits 30 bits
-    DevBuf status, ticket;
-    status.alloc(ceil_div(n, tile) * kRadix * (narrow ? 4 : 8) + 8, s);
-    ticket.alloc(sizeof(uint32_t) * 4, s);
+    // every pass gets its own look-back words (the tile count of the tile
+    // shape the dispatch launches: TILE == tile) and, after all of them, its
+    // own ticket; one clear before the first pass
+    const uint64_t pass_words = ceil_div(ceil_div(n, (uint64_t)tile) * kRadix * (narrow ? 4 : 8), (uint64_t)8);
+    const uint64_t np = shifts.size();
+    DevBuf status;
+    status.alloc((pass_words * np + ceil_div(np, (uint64_t)2) + 1) * 8, s);
+    uint32_t *tickets = reinterpret_cast<uint32_t *>(status.as<uint64_t>() + pass_words * np);
+    clear_lookback(status.as<uint64_t>(), pass_words * np + ceil_div(np, (uint64_t)2) + 1, tickets, s);
     bool inB = false;
+    uint64_t pass = 0;
     for (int sh : shifts) {
         const K *ki = inB ? kB : kA;
         const VT *vi = inB ? vB : vA;
         K *ko = inB ? kA : kB;
         VT *vo = inB ? vA : vB;
         const uint32_t *b = bases + (sh / kRadixBits) * kRadix;
+        void *st = status.as<uint64_t>() + pass * pass_words;
         if (narrow)
-            onesweep_dispatch<K, uint32_t, ROLE, VT>(tile, ki, vi, ko, vo, (uint32_t)n, sh, b, status.p,
-                                                 ticket.as<uint32_t>(), s);
+            onesweep_dispatch<K, uint32_t, ROLE, VT>(tile, ki, vi, ko, vo, (uint32_t)n, sh, b, st, tickets + pass,
+                                                 s);
         else
-            onesweep_dispatch<K, uint64_t, ROLE, VT>(tile, ki, vi, ko, vo, (uint32_t)n, sh, b, status.p,
-                                                 ticket.as<uint32_t>(), s);
+            onesweep_dispatch<K, uint64_t, ROLE, VT>(tile, ki, vi, ko, vo, (uint32_t)n, sh, b, st, tickets + pass,
+                                                 s);
         inB = !inB;
+        ++pass;
     }
     // status/ticket are released stream-ordered (or by hipFree, which waits)
     return inB;
