@@ -776,46 +776,54 @@ template <int NAX>
 __global__ __launch_bounds__(256) void chunk_class_kernel(EmitArgs a, int chunk_shift,
                                                           unsigned long long *__restrict__ cnt) {
     const int lane = lane_id();
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    // every lane of a wavefront runs the same number of rounds (wavefront sums below)
-    const uint64_t base0 = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(uint64_t)(kWave - 1));
+    // U points per lane and round, their loads issued together (indices
+    // clamped below n); every lane of a wavefront runs the same rounds
+    // (wavefront sums below)
+    constexpr int U = 2;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x * U;
+    const uint64_t base0 = ((uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(uint64_t)(kWave - 1))) * U;
     for (uint64_t kb = base0; kb < a.n; kb += stride) {
-        const uint64_t k = kb + lane;
-        const bool valid = k < a.n;
-        uint64_t b = 0, e = 0;
-        uint32_t pay = 0;
-        uint32_t rk[NAX > 0 ? NAX : 1];
-        if (valid) {
-            b = a.off[k];
-            e = a.off[k + 1];
-            pay = a.pay[k];
+        uint64_t bs[U], es[U];
+        uint32_t pays[U], rks[U][NAX > 0 ? NAX : 1];
 #pragma unroll
-            for (int ax = 0; ax < NAX; ++ax) rk[ax] = a.rs[(uint64_t)ax * a.n + k];
+        for (int u = 0; u < U; ++u) {
+            const uint64_t k0 = kb + (uint64_t)u * kWave + lane;
+            const uint64_t k = k0 < a.n ? k0 : (uint64_t)a.n - 1;
+            bs[u] = a.off[k];
+            es[u] = a.off[k + 1];
+            pays[u] = a.pay[k];
+#pragma unroll
+            for (int ax = 0; ax < NAX; ++ax) rks[u][ax] = a.rs[(uint64_t)ax * a.n + k];
         }
-        const bool has = valid && e > b;
-        const uint64_t c0 = b >> chunk_shift;
-        uint64_t v = 0, end0 = 0;
-        if (has) {
-            end0 = (c0 + 1) << chunk_shift;
-            if (end0 > e) end0 = e;
-            v = point_class_counts<NAX>(a, pay, rk, 0u, (uint32_t)(end0 - b));
-        }
-        // sum over the lanes sharing a first chunk, one atomic per chunk
-        uint64_t todo = __ballot(has);
-        while (todo) {
-            const int leader = __ffsll((unsigned long long)todo) - 1;
-            const uint64_t cl = read_uniform_lane(c0, leader);
-            const uint64_t same = __ballot(has && c0 == cl);
-            const uint64_t sum = wave_sum_u64(((same >> lane) & 1ull) ? v : 0ull);
-            if (lane == leader) atomicAdd(&cnt[cl], (unsigned long long)sum);
-            todo &= ~same;
-        }
-        // records past the first chunk (points straddling chunk ends)
-        if (has && end0 < e) {
-            for (uint64_t lo = end0; lo < e; lo += (1ull << chunk_shift)) {
-                const uint64_t hi = (lo + (1ull << chunk_shift) < e) ? lo + (1ull << chunk_shift) : e;
-                atomicAdd(&cnt[lo >> chunk_shift],
-                          (unsigned long long)point_class_counts<NAX>(a, pay, rk, (uint32_t)(lo - b), (uint32_t)(hi - b)));
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t k = kb + (uint64_t)u * kWave + lane;
+            const uint64_t b = bs[u], e = es[u];
+            const bool has = k < a.n && e > b;
+            const uint64_t c0 = b >> chunk_shift;
+            uint64_t v = 0, end0 = 0;
+            if (has) {
+                end0 = (c0 + 1) << chunk_shift;
+                if (end0 > e) end0 = e;
+                v = point_class_counts<NAX>(a, pays[u], rks[u], 0u, (uint32_t)(end0 - b));
+            }
+            // sum over the lanes sharing a first chunk, one atomic per chunk
+            uint64_t todo = __ballot(has);
+            while (todo) {
+                const int leader = __ffsll((unsigned long long)todo) - 1;
+                const uint64_t cl = read_uniform_lane(c0, leader);
+                const uint64_t same = __ballot(has && c0 == cl);
+                const uint64_t sum = wave_sum_u64(((same >> lane) & 1ull) ? v : 0ull);
+                if (lane == leader) atomicAdd(&cnt[cl], (unsigned long long)sum);
+                todo &= ~same;
+            }
+            // records past the first chunk (points straddling chunk ends)
+            if (has && end0 < e) {
+                for (uint64_t lo = end0; lo < e; lo += (1ull << chunk_shift)) {
+                    const uint64_t hi = (lo + (1ull << chunk_shift) < e) ? lo + (1ull << chunk_shift) : e;
+                    atomicAdd(&cnt[lo >> chunk_shift], (unsigned long long)point_class_counts<NAX>(
+                                                           a, pays[u], rks[u], (uint32_t)(lo - b), (uint32_t)(hi - b)));
+                }
             }
         }
     }
