@@ -13,6 +13,13 @@
  * worked examples of Sec. 2.2 and Sec. 3, closed forms and invariants) by the
  * tests.
  *
+ * Non-strict dominance (an extension for the ECDF use the paper names in
+ * Sec. 1.2): bit a of le_mask asks for d_a <= q_a instead of d_a < q_a on
+ * axis a.  On an expanded axis this is the strict comparison of the data
+ * point's rank with the query's rank plus one (there are then K + 1 possible
+ * ranks, written with ceil(log2(K + 1)) bits); on the last axis of Sec. 5 it
+ * is the opposite tie rule, data before queries on equal coordinates.
+ *
  * Readings taken where the paper leaves room (each is also listed in the
  * design notes):
  *   - the union of D and Q is their concatenation; |D| != |Q| is allowed;
@@ -64,9 +71,14 @@ static val_t F(const monoid_t *M, val_t a, val_t b) {
 /* ------------------------------------------------------------------------ */
 /* Plain definition.                                                         */
 
-static int dominated(int m, const double *d, const double *q) {
-    for (int k = 0; k < m; k++)
-        if (!(d[k] < q[k])) return 0;
+static int dominated(int m, const double *d, const double *q, int le_mask) {
+    for (int k = 0; k < m; k++) {
+        if ((le_mask >> k) & 1) {
+            if (!(d[k] <= q[k])) return 0;
+        } else if (!(d[k] < q[k])) {
+            return 0;
+        }
+    }
     return 1;
 }
 
@@ -78,11 +90,11 @@ static int has_nan(int64_t n, const double *x) {
 
 static int brute(int m, int64_t nD, const double *D, int64_t nQ,
                  const double *Q, const val_t *w, const monoid_t *M,
-                 val_t *out) {
+                 int le_mask, val_t *out) {
     for (int64_t j = 0; j < nQ; j++) {
         val_t acc = M->e;
         for (int64_t i = 0; i < nD; i++)
-            if (dominated(m, D + i * m, Q + j * m)) acc = F(M, acc, w[i]);
+            if (dominated(m, D + i * m, Q + j * m, le_mask)) acc = F(M, acc, w[i]);
         out[j] = acc;
     }
     return 0;
@@ -97,20 +109,32 @@ static int check_common(int m, int64_t nD, const double *D, int64_t nQ,
     return 0;
 }
 
-int oracle_brute_f64(int m, int64_t nD, const double *D, int64_t nQ,
-                     const double *Q, const double *w, int op, double e,
-                     double *out) {
+int oracle_brute_le_f64(int m, int64_t nD, const double *D, int64_t nQ,
+                        const double *Q, const double *w, int op, double e,
+                        int le_mask, double *out) {
     int rc = check_common(m, nD, D, nQ, Q, op);
     if (rc) return rc;
     if (op == ORACLE_COUNT || (nD > 0 && !w) || (nQ > 0 && !out)) return -1;
     monoid_t M = {1, op, {.f = e}};
     /* double and val_t share size and representation of the float member */
-    return brute(m, nD, D, nQ, Q, (const val_t *)w, &M, (val_t *)out);
+    return brute(m, nD, D, nQ, Q, (const val_t *)w, &M, le_mask, (val_t *)out);
+}
+
+int oracle_brute_f64(int m, int64_t nD, const double *D, int64_t nQ,
+                     const double *Q, const double *w, int op, double e,
+                     double *out) {
+    return oracle_brute_le_f64(m, nD, D, nQ, Q, w, op, e, 0, out);
 }
 
 int oracle_brute_i64(int m, int64_t nD, const double *D, int64_t nQ,
                      const double *Q, const int64_t *w, int op, int64_t e,
                      int64_t *out) {
+    return oracle_brute_le_i64(m, nD, D, nQ, Q, w, op, e, 0, out);
+}
+
+int oracle_brute_le_i64(int m, int64_t nD, const double *D, int64_t nQ,
+                        const double *Q, const int64_t *w, int op, int64_t e,
+                        int le_mask, int64_t *out) {
     int rc = check_common(m, nD, D, nQ, Q, op);
     if (rc) return rc;
     if (nQ > 0 && !out) return -1;
@@ -125,7 +149,7 @@ int oracle_brute_i64(int m, int64_t nD, const double *D, int64_t nQ,
             ww[i].i = w[i];
         }
     }
-    rc = brute(m, nD, D, nQ, Q, ww, &M, (val_t *)out);
+    rc = brute(m, nD, D, nQ, Q, ww, &M, le_mask, (val_t *)out);
     free(ww);
     return rc;
 }
@@ -234,8 +258,9 @@ typedef struct {
 } rec_t;
 
 typedef struct {
-    int nt;   /* tuple length */
-    int sec5; /* 1: order (tuple, x_m, queries first, ID); 0: (tuple, data first, ID) */
+    int nt;      /* tuple length */
+    int sec5;    /* 1: order (tuple, x_m, queries first, ID); 0: (tuple, data first, ID) */
+    int last_le; /* Sec. 5 with <= on the last axis: data before queries on equal x_m */
 } order_t;
 
 static int rec_cmp(const void *pa, const void *pb, void *pctx) {
@@ -248,7 +273,7 @@ static int rec_cmp(const void *pa, const void *pb, void *pctx) {
     if (o->sec5) {
         if (a->xm < b->xm) return -1;
         if (b->xm < a->xm) return 1;
-        if (a->is_query != b->is_query) return a->is_query ? -1 : 1;
+        if (a->is_query != b->is_query) return (a->is_query != o->last_le) ? -1 : 1;
     } else {
         if (a->is_query != b->is_query) return a->is_query ? 1 : -1;
     }
@@ -268,13 +293,28 @@ static int idval_cmp(const void *pa, const void *pb) {
     return (a->pos > b->pos) - (a->pos < b->pos);
 }
 
+/* Optional outputs of the construction beyond the per-query results. */
+typedef struct {
+    int le_mask;       /* bit a: <= on axis a (see the header comment) */
+    /* The final list of Sec. 4 (instructions 6m+6 .. 6m+9): E entries in
+     * nondecreasing ID order, each carrying the total of its ID.  NULL: not
+     * built.  shortcut: build it instead by the segmented broadcast of the
+     * maximum described before those instructions (valid when F(a, b) >= a). */
+    int64_t *agg_ids;
+    val_t *agg_vals;
+    int64_t agg_cap;
+    int shortcut;
+} extras_t;
+
 /*
  * The construction on n = nD + nQ points.  `nt` axes (the first nt of m) are
  * replaced by binary ranks and expanded; with sec5 the last axis stays real.
  */
 static int construct(int m, int64_t nD, const double *D, int64_t nQ,
                      const double *Q, const val_t *wD, const monoid_t *M,
-                     int sec5, val_t *out, int64_t *E_out, int *L_out) {
+                     int sec5, val_t *out, int64_t *E_out, int *L_out,
+                     const extras_t *X) {
+    const int le_mask = X ? X->le_mask : 0;
     const int64_t n = nD + nQ;
     const int nt = sec5 ? m - 1 : m;
     int rc = 0;
@@ -297,7 +337,11 @@ static int construct(int m, int64_t nD, const double *D, int64_t nQ,
         for (int64_t id = 0; id < n; id++) col[id] = COORD(id, k);
         rc = oracle_dense_rank(n, col, rank + k * n, &K);
         if (rc) goto done;
-        L[k] = oracle_bits_for(K); /* bin(rank, K): ceil(log2 K) digits */
+        /* bin(rank, K): ceil(log2 K) digits; with <= on this axis the
+         * queries' ranks move up by one, so K + 1 values occur */
+        L[k] = oracle_bits_for(K + ((le_mask >> k) & 1));
+        if ((le_mask >> k) & 1)
+            for (int64_t id = nD; id < n; id++) rank[k * n + id] += 1;
         if (L_out) L_out[k] = L[k];
     }
 
@@ -357,7 +401,7 @@ static int construct(int m, int64_t nD, const double *D, int64_t nQ,
     /* Sort in doubly lexicographic order (Sec. 5: then by the real last
      * coordinate, queries before data on equality; basic: data first). */
     {
-        order_t o = {nt, sec5};
+        order_t o = {nt, sec5, sec5 ? (le_mask >> (m - 1)) & 1 : 0};
         qsort_r(ed, (size_t)E, sizeof(rec_t), rec_cmp, &o);
     }
 
@@ -393,8 +437,48 @@ static int construct(int m, int64_t nD, const double *D, int64_t nQ,
         for (int64_t k = 0; k < E; k++) {
             if (k == 0 || a2[k].id != a2[k - 1].id) acc = M->e;
             acc = F(M, acc, a2[k].a);
+            a2[k].a = acc; /* A3: the scan tagged by ID */
             const int last = (k == E - 1) || a2[k + 1].id != a2[k].id;
             if (last && a2[k].id >= nD) out[a2[k].id - nD] = acc;
+        }
+    }
+    if (X && X->agg_ids) {
+        if (X->agg_cap < E) { rc = -4; goto done; }
+        if (!X->shortcut) {
+            /* A4: the reverse of A3, so IDs are nondecreasing and each ID's
+             * complete aggregate comes first in its run; H: the IDs shifted
+             * right by one (-inf first); A5: e wherever the ID equals its
+             * predecessor; then the segmented scan of A5 tagged by ID. */
+            val_t acc = M->e;
+            for (int64_t k = 0; k < E; k++) {
+                const idval_t *a4 = &a2[E - 1 - k];
+                const int has_h = k > 0;
+                const int64_t h = has_h ? a2[E - k].id : 0;
+                const val_t a5 = (has_h && h == a4->id) ? M->e : a4->a;
+                if (!has_h || h != a4->id) acc = M->e; /* a new run of equal IDs */
+                acc = F(M, acc, a5);
+                X->agg_ids[k] = a4->id;
+                X->agg_vals[k] = acc;
+            }
+        } else {
+            /* the segmented broadcast of the maximum over each ID run of A3
+             * (its last entry, when F(a, b) >= a), listed in the same
+             * nondecreasing ID order as the general tail */
+            int64_t k = 0;
+            while (k < E) {
+                int64_t r = k;
+                val_t mx = a2[k].a;
+                while (r + 1 < E && a2[r + 1].id == a2[k].id) {
+                    r++;
+                    const int gt = M->is_float ? a2[r].a.f > mx.f : a2[r].a.i > mx.i;
+                    if (gt) mx = a2[r].a;
+                }
+                for (int64_t t = k; t <= r; t++) {
+                    X->agg_ids[E - 1 - t] = a2[k].id;
+                    X->agg_vals[E - 1 - t] = mx;
+                }
+                k = r + 1;
+            }
         }
     }
 #undef COORD
@@ -409,18 +493,20 @@ done:
 
 static int run_f64(int m, int64_t nD, const double *D, int64_t nQ,
                    const double *Q, const double *w, int op, double e,
-                   double *out, int sec5, int64_t *E_out, int *L_out) {
+                   double *out, int sec5, int64_t *E_out, int *L_out,
+                   const extras_t *X) {
     int rc = check_common(m, nD, D, nQ, Q, op);
     if (rc) return rc;
     if (op == ORACLE_COUNT || (nD > 0 && !w) || (nQ > 0 && !out)) return -1;
     monoid_t M = {1, op, {.f = e}};
     return construct(m, nD, D, nQ, Q, (const val_t *)w, &M, sec5,
-                     (val_t *)out, E_out, L_out);
+                     (val_t *)out, E_out, L_out, X);
 }
 
 static int run_i64(int m, int64_t nD, const double *D, int64_t nQ,
                    const double *Q, const int64_t *w, int op, int64_t e,
-                   int64_t *out, int sec5, int64_t *E_out, int *L_out) {
+                   int64_t *out, int sec5, int64_t *E_out, int *L_out,
+                   const extras_t *X) {
     int rc = check_common(m, nD, D, nQ, Q, op);
     if (rc) return rc;
     if ((nD > 0 && op != ORACLE_COUNT && !w) || (nQ > 0 && !out)) return -1;
@@ -428,7 +514,7 @@ static int run_i64(int m, int64_t nD, const double *D, int64_t nQ,
     val_t *ww = (val_t *)malloc(sizeof(val_t) * (size_t)(nD > 0 ? nD : 1));
     if (!ww) return -3;
     for (int64_t i = 0; i < nD; i++) ww[i].i = (op == ORACLE_COUNT) ? 1 : w[i];
-    rc = construct(m, nD, D, nQ, Q, ww, &M, sec5, (val_t *)out, E_out, L_out);
+    rc = construct(m, nD, D, nQ, Q, ww, &M, sec5, (val_t *)out, E_out, L_out, X);
     free(ww);
     return rc;
 }
@@ -436,29 +522,55 @@ static int run_i64(int m, int64_t nD, const double *D, int64_t nQ,
 int oracle_dom_agg_f64(int m, int64_t nD, const double *D, int64_t nQ,
                        const double *Q, const double *w, int op, double e,
                        double *out, int64_t *E_out, int *L_out) {
-    return run_f64(m, nD, D, nQ, Q, w, op, e, out, 1, E_out, L_out);
+    return run_f64(m, nD, D, nQ, Q, w, op, e, out, 1, E_out, L_out, NULL);
 }
 
 int oracle_dom_agg_i64(int m, int64_t nD, const double *D, int64_t nQ,
                        const double *Q, const int64_t *w, int op, int64_t e,
                        int64_t *out, int64_t *E_out, int *L_out) {
-    return run_i64(m, nD, D, nQ, Q, w, op, e, out, 1, E_out, L_out);
+    return run_i64(m, nD, D, nQ, Q, w, op, e, out, 1, E_out, L_out, NULL);
 }
 
 int oracle_dom_agg_basic_f64(int m, int64_t nD, const double *D, int64_t nQ,
                              const double *Q, const double *w, int op,
                              double e, double *out, int64_t *E_out) {
-    return run_f64(m, nD, D, nQ, Q, w, op, e, out, 0, E_out, NULL);
+    return run_f64(m, nD, D, nQ, Q, w, op, e, out, 0, E_out, NULL, NULL);
 }
 
 int oracle_dom_agg_basic_i64(int m, int64_t nD, const double *D, int64_t nQ,
                              const double *Q, const int64_t *w, int op,
                              int64_t e, int64_t *out, int64_t *E_out) {
-    return run_i64(m, nD, D, nQ, Q, w, op, e, out, 0, E_out, NULL);
+    return run_i64(m, nD, D, nQ, Q, w, op, e, out, 0, E_out, NULL, NULL);
+}
+
+int oracle_dom_agg_ex_f64(int m, int64_t nD, const double *D, int64_t nQ,
+                          const double *Q, const double *w, int op, double e,
+                          int sec5, int le_mask, double *out, int64_t *E_out,
+                          int *L_out, int64_t *agg_ids, double *agg_vals,
+                          int64_t agg_cap, int shortcut) {
+    extras_t X = {le_mask, agg_ids, (val_t *)agg_vals, agg_cap, shortcut};
+    if (agg_ids && !agg_vals) return -1;
+    return run_f64(m, nD, D, nQ, Q, w, op, e, out, sec5, E_out, L_out, &X);
+}
+
+int oracle_dom_agg_ex_i64(int m, int64_t nD, const double *D, int64_t nQ,
+                          const double *Q, const int64_t *w, int op, int64_t e,
+                          int sec5, int le_mask, int64_t *out, int64_t *E_out,
+                          int *L_out, int64_t *agg_ids, int64_t *agg_vals,
+                          int64_t agg_cap, int shortcut) {
+    extras_t X = {le_mask, agg_ids, (val_t *)agg_vals, agg_cap, shortcut};
+    if (agg_ids && !agg_vals) return -1;
+    return run_i64(m, nD, D, nQ, Q, w, op, e, out, sec5, E_out, L_out, &X);
 }
 
 int oracle_transposed_sum_f64(int m, int64_t nD, const double *D, int64_t nQ,
                               const double *Q, const double *g, double *grad) {
+    return oracle_transposed_sum_le_f64(m, nD, D, nQ, Q, g, 0, grad);
+}
+
+int oracle_transposed_sum_le_f64(int m, int64_t nD, const double *D,
+                                 int64_t nQ, const double *Q, const double *g,
+                                 int le_mask, double *grad) {
     int rc = check_common(m, nD, D, nQ, Q, ORACLE_SUM);
     if (rc) return rc;
     if ((nQ > 0 && !g) || (nD > 0 && !grad)) return -1;
@@ -468,8 +580,9 @@ int oracle_transposed_sum_f64(int m, int64_t nD, const double *D, int64_t nQ,
     /* the roles swap: queries become data (weights g), data become queries */
     for (int64_t i = 0; i < nQ * m; i++) nd[i] = -Q[i];
     for (int64_t i = 0; i < nD * m; i++) nq[i] = -D[i];
-    rc = oracle_dom_agg_f64(m, nQ, nd, nD, nq, g, ORACLE_SUM, 0.0, grad, NULL,
-                            NULL);
+    /* d <= q on an axis  <=>  -q <= -d: the same le_mask applies */
+    rc = oracle_dom_agg_ex_f64(m, nQ, nd, nD, nq, g, ORACLE_SUM, 0.0, 1, le_mask,
+                               grad, NULL, NULL, NULL, NULL, 0, 0);
     free(nd);
     free(nq);
     return rc;

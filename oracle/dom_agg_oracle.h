@@ -14,7 +14,8 @@
  * 0..nD-1 in input order, queries nD..nD+nQ-1.  Queries carry the unit e as
  * their weight.  Dominance is strict in every coordinate (Sec. 1.2).
  *
- * Return codes: 0 ok, -1 bad argument, -2 NaN coordinate, -3 out of memory.
+ * Return codes: 0 ok, -1 bad argument, -2 NaN coordinate, -3 out of memory,
+ * -4 output list too short.
  */
 #ifndef DOM_AGG_ORACLE_H
 #define DOM_AGG_ORACLE_H
@@ -68,6 +69,39 @@ int oracle_dom_agg_basic_i64(int m, int64_t nD, const double *D, int64_t nQ,
  * d < q  <=>  -q < -d coordinate-wise. */
 int oracle_transposed_sum_f64(int m, int64_t nD, const double *D, int64_t nQ,
                               const double *Q, const double *g, double *grad);
+
+/* Non-strict dominance and the final list of Sec. 4.
+ *
+ * le_mask: bit a asks for D[i][a] <= Q[j][a] instead of < on axis a
+ * (0 = strict dominance everywhere, as above).
+ *
+ * oracle_dom_agg_ex_*: the construction (sec5 = 1: Sec. 5, sec5 = 0: basic
+ * Sec. 4) with le_mask; when agg_ids is not NULL it also writes the list the
+ * last instructions of Sec. 4 build (6m+6 .. 6m+9: sort by ID, shift,
+ * neutral_if_eq, segmented scan by ID): E entries in nondecreasing ID order
+ * (data IDs 0..nD-1, then queries nD..nD+nQ-1), each ID repeated once per
+ * record of its point, each entry the total of its ID.  shortcut = 1 builds
+ * the same list with the segmented broadcast of the maximum that Sec. 4
+ * offers when F(a, b) >= a.  agg_cap < E returns -4. */
+int oracle_brute_le_f64(int m, int64_t nD, const double *D, int64_t nQ,
+                        const double *Q, const double *w, int op, double e,
+                        int le_mask, double *out);
+int oracle_brute_le_i64(int m, int64_t nD, const double *D, int64_t nQ,
+                        const double *Q, const int64_t *w, int op, int64_t e,
+                        int le_mask, int64_t *out);
+int oracle_dom_agg_ex_f64(int m, int64_t nD, const double *D, int64_t nQ,
+                          const double *Q, const double *w, int op, double e,
+                          int sec5, int le_mask, double *out, int64_t *E_out,
+                          int *L_out, int64_t *agg_ids, double *agg_vals,
+                          int64_t agg_cap, int shortcut);
+int oracle_dom_agg_ex_i64(int m, int64_t nD, const double *D, int64_t nQ,
+                          const double *Q, const int64_t *w, int op, int64_t e,
+                          int sec5, int le_mask, int64_t *out, int64_t *E_out,
+                          int *L_out, int64_t *agg_ids, int64_t *agg_vals,
+                          int64_t agg_cap, int shortcut);
+int oracle_transposed_sum_le_f64(int m, int64_t nD, const double *D,
+                                 int64_t nQ, const double *Q, const double *g,
+                                 int le_mask, double *grad);
 
 /* Primitives, exposed so they can be checked against the paper's examples. */
 

@@ -13,7 +13,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SOURCES = ["dom_agg_oracle.c", "fenwick_pin.c"]
+_SOURCES = ["dom_agg_oracle.c", "fenwick_pin.c", "cdq3_pin.c"]
 _LIB_NAME = "liboracle.so"
 
 SUM, MAX, COUNT = 0, 1, 2
@@ -67,11 +67,20 @@ def _load():
     lib.oracle_bits_for.argtypes = [I64]
     lib.pin_fenwick2_f64.argtypes = [I64, P, I64, P, P, I, D, P]
     lib.pin_fenwick2_i64.argtypes = [I64, P, I64, P, P, I, I64, P]
+    lib.pin_cdq3_f64.argtypes = [I64, P, I64, P, P, I, D, I, P]
+    lib.pin_cdq3_i64.argtypes = [I64, P, I64, P, P, I, I64, I, P]
+    lib.oracle_brute_le_f64.argtypes = [I, I64, P, I64, P, P, I, D, I, P]
+    lib.oracle_brute_le_i64.argtypes = [I, I64, P, I64, P, P, I, I64, I, P]
+    lib.oracle_dom_agg_ex_f64.argtypes = [I, I64, P, I64, P, P, I, D, I, I, P, P, P, P, P, I64, I]
+    lib.oracle_dom_agg_ex_i64.argtypes = [I, I64, P, I64, P, P, I, I64, I, I, P, P, P, P, P, I64, I]
+    lib.oracle_transposed_sum_le_f64.argtypes = [I, I64, P, I64, P, P, I, P]
     for name in ("oracle_brute_f64", "oracle_brute_i64", "oracle_dom_agg_f64",
                  "oracle_dom_agg_i64", "oracle_dom_agg_basic_f64",
                  "oracle_dom_agg_basic_i64", "oracle_transposed_sum_f64",
                  "oracle_sscan_f64", "oracle_prefix_set", "oracle_dense_rank",
-                 "oracle_bits_for", "pin_fenwick2_f64", "pin_fenwick2_i64"):
+                 "oracle_bits_for", "pin_fenwick2_f64", "pin_fenwick2_i64",
+                 "pin_cdq3_f64", "pin_cdq3_i64", "oracle_brute_le_f64", "oracle_brute_le_i64",
+                 "oracle_dom_agg_ex_f64", "oracle_dom_agg_ex_i64", "oracle_transposed_sum_le_f64"):
         getattr(lib, name).restype = I
     _lib = lib
     return lib
@@ -89,6 +98,8 @@ def _coords(x, m):
 def _check(rc, what):
     if rc == -2:
         raise OracleError(f"{what}: NaN coordinate")
+    if rc == -4:
+        raise OracleError(f"{what}: output list too short")
     if rc != 0:
         raise OracleError(f"{what}: error {rc}")
 
@@ -120,7 +131,9 @@ def _weights(w, op, nD, weight_dtype):
     return w, is_float, src
 
 
-def _run(kind, m, D, Q, w, op, weight_dtype=None):
+def _run(kind, m, D, Q, w, op, weight_dtype=None, le_mask=0, agg=False, shortcut=False):
+    """kind: 'brute' (the definition), 'sec5' (the construction with the
+    Sec. 5 improvement) or 'basic' (the basic construction of Sec. 4)."""
     lib = _load()
     D = _coords(D, m)
     Q = _coords(Q, m)
@@ -129,58 +142,79 @@ def _run(kind, m, D, Q, w, op, weight_dtype=None):
     e = identity(op, wd)
     E = ctypes.c_int64(0)
     L = (ctypes.c_int * 8)()
-    if is_float:
-        out = np.empty(nQ, dtype=np.float64)
-        if kind == "brute":
-            rc = lib.oracle_brute_f64(m, nD, _ptr(D), nQ, _ptr(Q), _ptr(w), _OPS[op], float(e), _ptr(out))
-        elif kind == "sec5":
-            rc = lib.oracle_dom_agg_f64(m, nD, _ptr(D), nQ, _ptr(Q), _ptr(w), _OPS[op], float(e), _ptr(out),
-                                        ctypes.byref(E), L)
-        else:
-            rc = lib.oracle_dom_agg_basic_f64(m, nD, _ptr(D), nQ, _ptr(Q), _ptr(w), _OPS[op], float(e),
-                                              _ptr(out), ctypes.byref(E))
+    vt = np.float64 if is_float else np.int64
+    out = np.empty(nQ, dtype=vt)
+    ids = vals = None
+    if kind == "brute":
+        fn = lib.oracle_brute_le_f64 if is_float else lib.oracle_brute_le_i64
+        ev = float(e) if is_float else int(e)
+        rc = fn(m, nD, _ptr(D), nQ, _ptr(Q), _ptr(w), _OPS[op], ev, int(le_mask), _ptr(out))
     else:
-        out = np.empty(nQ, dtype=np.int64)
-        if kind == "brute":
-            rc = lib.oracle_brute_i64(m, nD, _ptr(D), nQ, _ptr(Q), _ptr(w), _OPS[op], int(e), _ptr(out))
-        elif kind == "sec5":
-            rc = lib.oracle_dom_agg_i64(m, nD, _ptr(D), nQ, _ptr(Q), _ptr(w), _OPS[op], int(e), _ptr(out),
-                                        ctypes.byref(E), L)
-        else:
-            rc = lib.oracle_dom_agg_basic_i64(m, nD, _ptr(D), nQ, _ptr(Q), _ptr(w), _OPS[op], int(e),
-                                              _ptr(out), ctypes.byref(E))
+        fn = lib.oracle_dom_agg_ex_f64 if is_float else lib.oracle_dom_agg_ex_i64
+        ev = float(e) if is_float else int(e)
+        sec5 = 1 if kind == "sec5" else 0
+        cap = 0
+        if agg:
+            # the size of the final list is E: one run of the construction to learn it
+            rc = fn(m, nD, _ptr(D), nQ, _ptr(Q), _ptr(w), _OPS[op], ev, sec5, int(le_mask), _ptr(out),
+                    ctypes.byref(E), L, None, None, 0, 0)
+            _check(rc, kind)
+            cap = int(E.value)
+            ids = np.empty(cap, dtype=np.int64)
+            vals = np.empty(cap, dtype=vt)
+        rc = fn(m, nD, _ptr(D), nQ, _ptr(Q), _ptr(w), _OPS[op], ev, sec5, int(le_mask), _ptr(out),
+                ctypes.byref(E), L, _ptr(ids) if agg else None, _ptr(vals) if agg else None, cap,
+                1 if shortcut else 0)
     _check(rc, kind)
-    return out, int(E.value), [int(L[i]) for i in range(max(m - 1, 0))]
+    nL = max(m - 1, 0) if kind == "sec5" else m
+    return out, int(E.value), [int(L[i]) for i in range(nL)], ids, vals
 
 
-def brute(m, D, Q, w=None, op="sum", weight_dtype=None):
+def brute(m, D, Q, w=None, op="sum", weight_dtype=None, le_mask=0):
     """Plain definition (Sec. 1.2): for each query, F over the weights of the
-    data points it strictly dominates.  O(|D||Q|m)."""
-    return _run("brute", m, D, Q, w, op, weight_dtype)[0]
+    data points it strictly dominates (or dominates with <= on the axes whose
+    bit is set in le_mask).  O(|D||Q|m)."""
+    return _run("brute", m, D, Q, w, op, weight_dtype, le_mask)[0]
 
 
-def construction(m, D, Q, w=None, op="sum", weight_dtype=None, return_stats=False):
+def construction(m, D, Q, w=None, op="sum", weight_dtype=None, return_stats=False, le_mask=0):
     """The paper's construction with the Sec. 5 improvement.  With
     return_stats, also returns (E, L): the expanded record count and the bit
     width of each expanded axis."""
-    out, E, L = _run("sec5", m, D, Q, w, op, weight_dtype)
+    out, E, L, _, _ = _run("sec5", m, D, Q, w, op, weight_dtype, le_mask)
     return (out, E, L) if return_stats else out
 
 
-def construction_basic(m, D, Q, w=None, op="sum", weight_dtype=None, return_E=False):
+def construction_basic(m, D, Q, w=None, op="sum", weight_dtype=None, return_E=False, le_mask=0,
+                       return_stats=False):
     """The basic construction of Sec. 4 (all m axes expanded)."""
-    out, E, _ = _run("basic", m, D, Q, w, op, weight_dtype)
+    out, E, L, _, _ = _run("basic", m, D, Q, w, op, weight_dtype, le_mask)
+    if return_stats:
+        return out, E, L
     return (out, E) if return_E else out
 
 
-def transposed_sum(m, D, Q, g):
-    """grad[i] = sum of g[j] over queries j that strictly dominate D[i]."""
+def final_list(m, D, Q, w=None, op="sum", weight_dtype=None, le_mask=0, shortcut=False, basic=False):
+    """The list the last instructions of Sec. 4 build: (ids, vals), E entries
+    in nondecreasing ID order (data IDs 0..|D|-1, then queries |D|..), each
+    ID once per record of its point, each value the total of its ID.
+    shortcut: built by the segmented broadcast of the maximum instead (valid
+    when F(a, b) >= a)."""
+    _, _, _, ids, vals = _run("basic" if basic else "sec5", m, D, Q, w, op, weight_dtype, le_mask,
+                              agg=True, shortcut=shortcut)
+    return ids, vals
+
+
+def transposed_sum(m, D, Q, g, le_mask=0):
+    """grad[i] = sum of g[j] over queries j that dominate D[i] (strictly, or
+    with <= on the axes of le_mask)."""
     lib = _load()
     D = _coords(D, m)
     Q = _coords(Q, m)
     g = np.ascontiguousarray(g, dtype=np.float64)
     grad = np.empty(D.shape[0], dtype=np.float64)
-    rc = lib.oracle_transposed_sum_f64(m, D.shape[0], _ptr(D), Q.shape[0], _ptr(Q), _ptr(g), _ptr(grad))
+    rc = lib.oracle_transposed_sum_le_f64(m, D.shape[0], _ptr(D), Q.shape[0], _ptr(Q), _ptr(g), int(le_mask),
+                                          _ptr(grad))
     _check(rc, "transposed_sum")
     return grad
 
@@ -239,4 +273,36 @@ def fenwick2(D, Q, w=None, op="sum", weight_dtype=None):
         out = np.empty(nQ, dtype=np.int64)
         rc = lib.pin_fenwick2_i64(nD, _ptr(D), nQ, _ptr(Q), _ptr(w), int(op_ == "max"), int(e), _ptr(out))
     _check(rc, "fenwick2")
+    return out
+
+
+def sweep(m, D, Q, w=None, op="sum", weight_dtype=None, le_mask=0):
+    """Textbook offline divide and conquer for m <= 3 (a pin, not the
+    construction): sort by the first axis, split in halves, settle the pairs
+    across the halves while merging by the second axis with a Fenwick tree
+    over ranks of the third.  Smaller m pad constant axes compared with <=."""
+    if m > 3:
+        raise OracleError("sweep: m <= 3")
+    lib = _load()
+    D = _coords(D, m)
+    Q = _coords(Q, m)
+    nD, nQ = D.shape[0], Q.shape[0]
+    if m < 3:
+        D = np.ascontiguousarray(np.hstack([D, np.zeros((nD, 3 - m))]))
+        Q = np.ascontiguousarray(np.hstack([Q, np.zeros((nQ, 3 - m))]))
+        le_mask = int(le_mask) | sum(1 << a for a in range(m, 3))
+    if op == "count":
+        w = np.ones(nD, dtype=np.int64)
+        op_ = "sum"
+    else:
+        op_ = op
+    w, is_float, wd = _weights(w, op_, nD, weight_dtype)
+    e = identity(op_, wd)
+    if is_float:
+        out = np.empty(nQ, dtype=np.float64)
+        rc = lib.pin_cdq3_f64(nD, _ptr(D), nQ, _ptr(Q), _ptr(w), int(op_ == "max"), float(e), int(le_mask), _ptr(out))
+    else:
+        out = np.empty(nQ, dtype=np.int64)
+        rc = lib.pin_cdq3_i64(nD, _ptr(D), nQ, _ptr(Q), _ptr(w), int(op_ == "max"), int(e), int(le_mask), _ptr(out))
+    _check(rc, "sweep")
     return out
