@@ -85,8 +85,23 @@ enum {
      * replay it on later calls with the same arguments. */
     DOM_AGG_GRAPH = 4,
     /* Skip the autotuner and use the built-in tile and digit widths. */
-    DOM_AGG_NO_TUNE = 8
+    DOM_AGG_NO_TUNE = 8,
+    /* The basic variant of Sec. 4 instead of the Sec. 5 improvement: every
+     * axis is replaced by binary ranks and expanded (n log^m n records), and
+     * inside a run of equal tuples data precede queries.  Same results; a
+     * second, independent GPU path.  m <= 3. */
+    DOM_AGG_BASIC = 16
 };
+
+/* Non-strict dominance on chosen axes: with DOM_AGG_LE(a) in the flags of
+ * dom_agg_plan or dom_agg_run, axis a (0-based, a < m) compares d_a <= q_a
+ * instead of d_a < q_a (e.g. all axes for the multivariate empirical CDF,
+ * the statistics use named in Sec. 1.2).  On an expanded axis the queries'
+ * dense ranks move up by one, so that the strict comparison of Lemma 1
+ * applies to (rank of d, rank of q + 1) with ceil(log2(K + 1)) digits; on the
+ * last axis (Sec. 5) data precede queries on equal coordinates.  The
+ * backward is then the transpose of that relation. */
+#define DOM_AGG_LE(axis) (0x100u << (axis))
 
 typedef struct dom_agg_plan_s *dom_agg_plan_t;
 
@@ -103,11 +118,14 @@ typedef struct {
     int32_t digit_bits;    /* radix digit width chosen for the record sort */
     int32_t sort_tile;     /* records per workgroup tile in the record sort */
     int32_t scan_tile;     /* records per workgroup tile in the segmented scans */
-    int32_t regroup_slots; /* level-tuple slots of the regrouping; 0 = atomic F instead */
+    int32_t regroup_slots; /* level-tuple slots of the regrouping table; 0 = the
+                              compact table (one place per record) */
     int32_t sort_classes;  /* key-length classes the record sort is split into (1 = none) */
     int64_t sort_class_records[4]; /* records per class (class c is sorted with
                                       sort_passes - sort_classes + 1 + c passes) */
     size_t workspace_bytes;/* device memory held by the plan */
+    uint32_t le_mask;      /* bit a: <= on axis a (DOM_AGG_LE) */
+    int32_t basic;         /* 1: the basic variant (DOM_AGG_BASIC), L has m entries */
 } dom_agg_plan_info;
 
 /*
@@ -139,11 +157,13 @@ dom_agg_status dom_agg_set_allocator(dom_agg_alloc_fn alloc, dom_agg_release_fn 
  *               k owns data rows d_offsets[k] .. d_offsets[k+1]-1.
  *   q_offsets   (host) likewise for queries.  Points of different instances
  *               never interact.
- *   flags       DOM_AGG_KEEP / DOM_AGG_RECOMPUTE | DOM_AGG_GRAPH | DOM_AGG_NO_TUNE.
+ *   flags       DOM_AGG_KEEP / DOM_AGG_RECOMPUTE | DOM_AGG_GRAPH | DOM_AGG_NO_TUNE
+ *               | DOM_AGG_BASIC | DOM_AGG_LE(a) for any axes a < m.
  *   stream      hipStream_t.
  *
  * Errors: EINVAL (m, counts, offsets, NULL pointers with nonzero counts,
- * unknown flags or dtype), ENAN, ETOOBIG, ENOMEM, ENODEV, EHIP.
+ * unknown flags or dtype), EUNSUPPORTED (DOM_AGG_BASIC with m = 4), ENAN,
+ * ETOOBIG, ENOMEM, ENODEV, EHIP.
  */
 dom_agg_status dom_agg_plan(dom_agg_plan_t *plan, int m, dom_agg_dtype coord_dtype,
                             const void *d_coords, const void *q_coords, int64_t n_inst,
@@ -199,7 +219,8 @@ dom_agg_status dom_agg_backward(dom_agg_plan_t plan, dom_agg_dtype grad_dtype,
  *   m, coord_dtype, d_coords, q_coords, n_inst, d_offsets, q_offsets: as
  *       for dom_agg_plan;
  *   op, weight_dtype, weights, out: as for dom_agg_forward;
- *   flags    0 or DOM_AGG_NO_TUNE.
+ *   flags    0 or DOM_AGG_NO_TUNE, | DOM_AGG_BASIC, | DOM_AGG_LE(a) for any
+ *            axes a < m.
  *   stream   hipStream_t; the call synchronises with it while it sizes the
  *            flat map, and returns with the scan and the regrouping enqueued.
  *

@@ -22,7 +22,12 @@ OPS = {"sum": SUM, "max": MAX, "count": COUNT}
 # dom_agg_dtype
 I32, I64, F32, F64 = 0, 1, 2, 3
 # plan flags
-KEEP, RECOMPUTE, GRAPH, NO_TUNE = 0, 2, 4, 8
+KEEP, RECOMPUTE, GRAPH, NO_TUNE, BASIC = 0, 2, 4, 8, 16
+
+
+def LE(axis: int) -> int:
+    """DOM_AGG_LE(axis): <= instead of < on that axis."""
+    return 0x100 << axis
 
 # exported functions, in the order include/dom_agg.h declares them
 EXPORTS = (
@@ -65,11 +70,13 @@ class PlanInfo(ctypes.Structure):
         ("sort_classes", ctypes.c_int32),
         ("sort_class_records", ctypes.c_int64 * 4),
         ("workspace_bytes", ctypes.c_size_t),
+        ("le_mask", ctypes.c_uint32),
+        ("basic", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("L", "sort_class_records")}
-        d["L"] = [self.L[i] for i in range(max(self.m - 1, 0))]
+        d["L"] = [self.L[i] for i in range(self.m if self.basic else max(self.m - 1, 0))]
         d["sort_class_records"] = [self.sort_class_records[i] for i in range(self.sort_classes)]
         return d
 

@@ -282,35 +282,25 @@ __device__ __forceinline__ V read_lane(V v, int src) {
 }
 
 // ---------------------------------------------------------------------------
-// Atomic F into global memory (the regrouping by query / data row).
+// Compensated fp32 sum.  A value is the unevaluated pair hi + lo with
+// |lo| <= ulp(hi) / 2; adding two of them is Knuth's TwoSum on the high parts
+// followed by a renormalisation (Fast2Sum), all in fp32 arithmetic.  Long
+// chains of fp32 additions (a segment that spans thousands of scan tiles, a
+// carry folded across all of them) then keep an error of a few units in the
+// last place of the result instead of one that grows with the chain.  The
+// sequence of additions is what fixes the result, so results repeat bit for
+// bit whenever the order of additions does.
+struct F32c {
+    float hi, lo;
+};
 
-__device__ __forceinline__ void atomic_sum(int64_t *p, int64_t v) {
-    atomicAdd(reinterpret_cast<unsigned long long *>(p), (unsigned long long)v);
-}
-__device__ __forceinline__ void atomic_sum(float *p, float v) { unsafeAtomicAdd(p, v); }
-__device__ __forceinline__ void atomic_sum(double *p, double v) { unsafeAtomicAdd(p, v); }
-
-__device__ __forceinline__ void atomic_max(int32_t *p, int32_t v) { atomicMax(p, v); }
-__device__ __forceinline__ void atomic_max(int64_t *p, int64_t v) {
-    atomicMax(reinterpret_cast<long long *>(p), (long long)v);
-}
-// IEEE floats: non-negative values order like signed integers of their bits,
-// negative values order reversed like unsigned integers of their bits.
-__device__ __forceinline__ void atomic_max(float *p, float v) {
-    v = v + 0.0f;  // -0 -> +0
-    const int32_t b = __float_as_int(v);
-    if (b >= 0)
-        atomicMax(reinterpret_cast<int *>(p), b);
-    else
-        atomicMin(reinterpret_cast<unsigned int *>(p), (unsigned int)b);
-}
-__device__ __forceinline__ void atomic_max(double *p, double v) {
-    v = v + 0.0;
-    const long long b = __double_as_longlong(v);
-    if (b >= 0)
-        atomicMax(reinterpret_cast<long long *>(p), b);
-    else
-        atomicMin(reinterpret_cast<unsigned long long *>(p), (unsigned long long)b);
+__device__ __forceinline__ F32c f32c_add(F32c a, F32c b) {
+    const float s = a.hi + b.hi;
+    const float bb = s - a.hi;
+    const float err = (a.hi - (s - bb)) + (b.hi - bb);
+    const float lo = a.lo + b.lo + err;
+    const float hi = s + lo;
+    return F32c{hi, lo - (hi - s)};
 }
 
 }  // namespace domagg

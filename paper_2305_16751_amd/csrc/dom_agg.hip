@@ -243,7 +243,7 @@ uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 constexpr int kBlock = 256;
 constexpr uint64_t kMaxRecords = (1ull << 32) - (1ull << 20);
 // slot-mode regrouping is used when the level-tuple table is small and dense
-// enough; beyond these, partials are combined with atomics
+// enough; beyond these, the compact layout (one place per record)
 constexpr uint64_t kMaxSlots = 1024;
 constexpr uint64_t kMaxSlotBytes = 64ull << 30;
 
@@ -256,6 +256,10 @@ struct dom_agg_plan_s {
     int device = 0;
     int m = 0, nax = 0;
     uint32_t flags = 0;
+    // bit a: <= instead of < on axis a (DOM_AGG_LE(a))
+    uint32_t le_mask = 0;
+    // the basic variant of Sec. 4 (DOM_AGG_BASIC): every axis expanded
+    bool basic = false;
     int64_t n_inst = 1, nD = 0, nQ = 0, n = 0;
     bool batched = false;
     int inst_bits = 0;
@@ -295,10 +299,11 @@ struct dom_agg_plan_s {
     const void *w_src = nullptr;
     dom_agg_dtype w_dt = DOM_AGG_F32;
     DevBuf rw, wv;
-    // regrouping: level-tuple slots (slot mode) or atomic F
+    // regrouping: level-tuple slots (slot mode) or one place per record
+    // (compact mode, with the per-slot state cstate)
     uint32_t n_slots = 1;
     bool use_slots = true;
-    DevBuf part;
+    DevBuf part, cstate;
     // sorted records (KEEP)
     DevBuf rkeys, rvals;
     // look-back words and ticket of the forward/backward scans
@@ -313,7 +318,7 @@ struct dom_agg_plan_s {
 
     size_t workspace() const {
         return off.bytes + rs.bytes + pay.bytes + inst_s.bytes + rank.bytes + inst_of_slot.bytes + ltab.bytes +
-               dinv.bytes + qinv.bytes + perm.bytes + rw.bytes + wv.bytes + cdf_d.bytes + cdf_q.bytes + part.bytes + rkeys.bytes + rvals.bytes + scan_status.bytes + scan_ticket.bytes + ed_counter.bytes;
+               dinv.bytes + qinv.bytes + perm.bytes + rw.bytes + wv.bytes + cdf_d.bytes + cdf_q.bytes + part.bytes + cstate.bytes + rkeys.bytes + rvals.bytes + scan_status.bytes + scan_ticket.bytes + ed_counter.bytes;
     }
     SlotMap slot_map() const {
         SlotMap sm{};
@@ -548,7 +553,7 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
     // m = 2: the last axis is sorted with 64-bit payloads carrying each
     // point's rank and record payload (extract_sigma_kernel), after the key
     // layout is known; the count pass then reads them in sequence
-    const bool sigv = nax == 1;
+    const bool sigv = nax == 1 && !P->basic;
     kA.alloc((size_t)n * sizeof(KP), s);
     kB.alloc((size_t)n * sizeof(KP), s);
     vA.alloc((size_t)n * 4, s);
@@ -558,9 +563,9 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
         kcount.alloc((size_t)nax * ni * 4, s);
         fill(kcount.as<uint32_t>(), (uint64_t)nax * ni, 0u, s);
         P->permuted = true;
-        if (nax == 1) pr.alloc((size_t)n * 8, s);
+        if (sigv) pr.alloc((size_t)n * 8, s);
         else ppos.alloc((size_t)n * 4, s);
-        if (nax == 1 && !P->batched) {
+        if (sigv && !P->batched) {
             P->cdf_d.alloc((size_t)n * 4, s);
             P->cdf_q.alloc((size_t)n * 4, s);
         }
@@ -583,10 +588,12 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
 
     // expanded axes first, the real (last) axis last
     for (int axis = 0; axis < (sigv ? 1 : m); ++axis) {
+        // (the last axis with <=: data before queries on equal coordinates)
+        const bool data_first = !P->basic && axis == m - 1 && ((P->le_mask >> axis) & 1u);
         launch("extract_keys", s, [&] {
             extract_keys_kernel<KP, C, kBlock><<<ext_blocks, kBlock, 0, s>>>(
                 qq, dq, m, axis, nQ, n, inst_of_slot.as<uint32_t>(), axis > 0 ? ppos.as<uint32_t>() : nullptr,
-                kA.as<KP>(), vA.as<uint32_t>(), passes, part.as<uint32_t>(), nanflag.as<uint32_t>());
+                kA.as<KP>(), vA.as<uint32_t>(), passes, part.as<uint32_t>(), nanflag.as<uint32_t>(), data_first);
         });
         reduce_hist(part.as<uint32_t>(), (int)ext_blocks, passes, counts.as<uint32_t>(), bases.as<uint32_t>(), s);
         const size_t cb = (size_t)passes * kRadix * 4;
@@ -618,6 +625,7 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
             rp.cdf_q = P->cdf_q.as<uint32_t>();
             rp.dinv = P->dinv.as<uint32_t>();
             rp.qinv = P->qinv.as<uint32_t>();
+            rp.nq_le = (P->le_mask & 1u) ? nQ : 0u;
             // (2048-element tiles: the rank scan's scattered per-point
             // stores want more resident tiles than its loads want long ones)
             scan_launch<RankProblem<KP, true>, 8>(
@@ -626,6 +634,7 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
         } else if (axis < nax) {
             RankProblem<KP> rp{sk.as<KP>(), sv.as<uint32_t>(), rank.as<uint32_t>() + (size_t)axis * n,
                                kcount.as<uint32_t>() + (size_t)axis * ni, n, (uint32_t)ni};
+            rp.nq_le = ((P->le_mask >> axis) & 1u) ? nQ : 0u;
             scan_launch<RankProblem<KP>, 8>(
                 "rank_scan", rp, n, scan_status.as<uint64_t>(), scan_status.bytes / 8,
                 scan_ticket.as<uint32_t>(), s);
@@ -633,6 +642,17 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
             sig_keys = std::move(sk);
             sig_slots = std::move(sv);
         }
+    }
+    if (P->basic) {
+        // every axis was ranked; the flat map walks data first, then queries
+        if (!ppos.p || nax != m) fail(DOM_AGG_EHIP, "internal: basic variant without internal slots");
+        sig_keys.alloc((size_t)n * sizeof(KP), s);
+        sig_slots.alloc((size_t)n * 4, s);
+        launch("basic_order", s, [&] {
+            basic_order_kernel<KP><<<grid_for(n), kBlock, 0, s>>>(nQ, n, inst_of_slot.as<uint32_t>(),
+                                                                 ppos.as<uint32_t>(), sig_keys.as<KP>(),
+                                                                 sig_slots.as<uint32_t>());
+        });
     }
 
     // Bit widths per instance and axis (ceil(log2 K)), and the record key layout.
@@ -645,7 +665,8 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
         for (int a = 0; a < nax; ++a) {
             int lm = 0;
             for (int64_t k = 0; k < ni; ++k) {
-                const int L = bits_for(h[(size_t)a * ni + k]);
+                // (with <= the queries' ranks reach K: K + 1 values)
+                const int L = bits_for((uint64_t)h[(size_t)a * ni + k] + ((P->le_mask >> a) & 1u));
                 lt[(size_t)a * ni + k] = (uint8_t)L;
                 lm = std::max(lm, L);
             }
@@ -680,7 +701,8 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
                 using W = std::remove_const_t<std::remove_pointer_t<decltype(w)>>;
                 extract_sigma_kernel<KP, C, W, kBlock><<<ext_blocks, kBlock, 0, s>>>(
                     qq, dq, 1, nQ, n, inst_of_slot.as<uint32_t>(), pr.as<uint64_t>(), w, P->inline_w, kA.as<KP>(),
-                    wA.as<uint64_t>(), passes, part.as<uint32_t>(), nanflag.as<uint32_t>());
+                    wA.as<uint64_t>(), passes, part.as<uint32_t>(), nanflag.as<uint32_t>(),
+                    ((P->le_mask >> 1) & 1u) != 0);
             };
             if (P->inline_w && P->w_dt == DOM_AGG_I32) go(static_cast<const int32_t *>(P->w_src));
             else go(P->inline_w ? static_cast<const float *>(P->w_src) : static_cast<const float *>(nullptr));
@@ -794,6 +816,7 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
     } else {
         switch (nax) {
             case 0: count(std::integral_constant<int, 0>{}); break;
+            case 1: count(std::integral_constant<int, 1>{}); break;
             case 2: count(std::integral_constant<int, 2>{}); break;
             default: count(std::integral_constant<int, 3>{}); break;
         }
@@ -843,7 +866,8 @@ void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &ou
     };
     // m = 2 with classes: the digit histograms come from the rank CDFs, one
     // thread per tree node, instead of one update per record in the flat map
-    const bool node_hist = cls && P->cdf_d.p && P->m == 2;
+    // (not with <= on the first axis: the rank CDFs are of the unshifted ranks)
+    const bool node_hist = cls && P->cdf_d.p && P->m == 2 && !(P->le_mask & 1u);
     // the flat map's workgroups: as many as are resident at once (each takes
     // a fixed share of the chunks)
     unsigned grid = 1;
@@ -1038,6 +1062,8 @@ void records_for_call(Plan *P, hipStream_t s, DevBuf &k, DevBuf &v, const void *
 RegroupArgs regroup_args(const Plan *P, bool queries) {
     RegroupArgs r{};
     r.inv = P->permuted ? (queries ? P->qinv.as<uint32_t>() : P->dinv.as<uint32_t>()) : nullptr;
+    r.cstate = P->cstate.p ? P->cstate.as<uint4>() + (queries ? 0 : P->nQ) : nullptr;
+    r.cap = (uint64_t)(queries ? P->E - P->E_D : P->E_D);
     r.rank = P->rank.as<uint32_t>();
     r.inst_of_slot = P->inst_of_slot.as<uint32_t>();
     r.ltab = P->ltab.as<uint8_t>();
@@ -1055,6 +1081,10 @@ template <class V, int OP>
 void regroup(const Plan *P, bool queries, const V *part, V *out, hipStream_t s) {
     const RegroupArgs ra = regroup_args(P, queries);
     const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(ceil_div(ra.nout, kBlock), 8192));
+    if (!P->use_slots) {
+        launch("regroup", s, [&] { regroup_compact_kernel<V, OP><<<grid, kBlock, 0, s>>>(ra, P->nax, part, out); });
+        return;
+    }
     auto go = [&](auto nax_c) {
         constexpr int NAX = decltype(nax_c)::value;
         launch("regroup", s, [&] { regroup_kernel<V, OP, NAX><<<grid, kBlock, 0, s>>>(ra, part, out); });
@@ -1078,14 +1108,31 @@ V host_identity() {
 }
 
 // The plan's per-call buffers, sized before any graph capture: inputs in
-// internal order, and the slot table of the regrouping (or, in atomic mode,
-// the atomic target in internal order).
+// internal order, and the table of the regrouping (slot or compact layout).
 void ensure_part(Plan *P, size_t vbytes, hipStream_t s) {
     const size_t rows = (size_t)std::max(P->nQ, P->nD);
     if (P->permuted && P->perm.bytes < rows * 8) P->perm.alloc(rows * 8, s);
     if (P->nax == 0) return;
-    const size_t need = P->use_slots ? (size_t)P->n_slots * rows * vbytes : rows * vbytes;
+    const size_t places = (size_t)std::max(P->E - P->E_D, P->E_D);
+    const size_t need = P->use_slots ? (size_t)P->n_slots * rows * vbytes : std::max<size_t>(places, 1) * vbytes;
     if (P->part.bytes < need) P->part.alloc(need, s);
+}
+
+// Where a scan stores the partials of queries (or data points): the
+// regrouping table, or out itself when every point has one record (m = 1).
+template <class V>
+PartDest<V> part_dest(const Plan *P, bool queries, V *table) {
+    PartDest<V> d{};
+    d.part = table;
+    d.stride = (uint64_t)(queries ? P->nQ : P->nD);
+    if (P->nax > 0 && !P->use_slots) {
+        d.cstate = P->cstate.as<uint4>() + (queries ? 0 : P->nQ);
+        d.cap = (uint64_t)(queries ? P->E - P->E_D : P->E_D);
+    } else {
+        d.cstate = nullptr;
+        d.cap = (uint64_t)(P->nax == 0 ? 1 : P->n_slots) * d.stride;
+    }
+    return d;
 }
 
 template <class T>
@@ -1116,15 +1163,9 @@ void forward_run(Plan *P, const void *kp, const uint32_t *vp, const void *w, voi
     }
     V *const res = static_cast<V *>(out);
     fp.sm = P->slot_map();
-    fp.stride = (uint64_t)P->nQ;
-    if (P->use_slots) {
-        // m = 1: every query has exactly one record, so it is stored in place
-        fp.part = P->nax == 0 ? res : P->part.as<V>();
-    } else {
-        fp.part = nullptr;
-        fp.out = P->permuted ? P->part.as<V>() : res;
-        fill(fp.out, (uint64_t)P->nQ, host_identity<V, OP>(), s);
-    }
+    // m = 1: every query has exactly one record, so it is stored in place
+    fp.q = part_dest<V>(P, true, P->nax == 0 ? res : P->part.as<V>());
+    fp.d = PartDest<V>{};
     using FP = ForwardProblem<K, W, V, OP, INL>;
     if (P->tune.scan_items == 8 || sizeof(K) == 8)
         scan_launch<FP, 8>("forward_scan", fp, (uint64_t)P->E, P->scan_status.as<uint64_t>(), P->scan_words,
@@ -1132,8 +1173,7 @@ void forward_run(Plan *P, const void *kp, const uint32_t *vp, const void *w, voi
     else
         scan_launch<FP, 16>("forward_scan", fp, (uint64_t)P->E, P->scan_status.as<uint64_t>(), P->scan_words,
                             P->scan_ticket.as<uint32_t>(), s);
-    if (P->use_slots && P->nax > 0) regroup<V, OP>(P, true, P->part.as<V>(), res, s);
-    else if (!P->use_slots && P->permuted) scatter(P->part.as<V>(), P->qinv.as<uint32_t>(), res, (uint64_t)P->nQ, s);
+    if (P->nax > 0) regroup<V, OP>(P, true, P->part.as<V>(), res, s);
 }
 
 // Records that carry weights were built for one (op, weight dtype); the
@@ -1180,24 +1220,16 @@ void backward_typed(Plan *P, const void *kp, const uint32_t *vp, const void *g, 
     }
     G *const res = static_cast<G *>(grad);
     bp.sm = P->slot_map();
-    bp.stride = (uint64_t)P->nD;
+    bp.d = part_dest<G>(P, false, P->nax == 0 ? res : P->part.as<G>());
     bp.ng = (uint64_t)P->nQ;
     bp.E = (uint64_t)P->E;
-    if (P->use_slots) {
-        bp.part = P->nax == 0 ? res : P->part.as<G>();
-    } else {
-        bp.part = nullptr;
-        bp.grad = P->permuted ? P->part.as<G>() : res;
-        fill(bp.grad, (uint64_t)P->nD, G(0), s);
-    }
     if (P->tune.scan_items == 8 || sizeof(K) == 8)
         scan_launch<BackwardProblem<K, G>, 8>("backward_scan", bp, (uint64_t)P->E, P->scan_status.as<uint64_t>(),
                                               P->scan_words, P->scan_ticket.as<uint32_t>(), s);
     else
         scan_launch<BackwardProblem<K, G>, 16>("backward_scan", bp, (uint64_t)P->E, P->scan_status.as<uint64_t>(),
                                                P->scan_words, P->scan_ticket.as<uint32_t>(), s);
-    if (P->use_slots && P->nax > 0) regroup<G, OP_SUM>(P, false, P->part.as<G>(), res, s);
-    else if (!P->use_slots && P->permuted) scatter(P->part.as<G>(), P->dinv.as<uint32_t>(), res, (uint64_t)P->nD, s);
+    if (P->nax > 0) regroup<G, OP_SUM>(P, false, P->part.as<G>(), res, s);
 }
 
 // Runs `body` directly, or through the plan's HIP graph in DOM_AGG_GRAPH mode.
@@ -1323,6 +1355,42 @@ void tune_plan(Plan *P, hipStream_t s) {
 }
 
 
+// Per-slot state of the compact regrouping layout (record counts, their
+// exclusive sums per kind of point, and the selecting digits of the ranks).
+void build_compact_state(Plan *P, hipStream_t s) {
+    const uint64_t n = (uint64_t)P->n;
+    P->cstate.alloc(n * sizeof(uint4), s);
+    CompactStateProblem cp{};
+    cp.rank = P->rank.as<uint32_t>();
+    cp.inst_of_slot = P->inst_of_slot.as<uint32_t>();
+    cp.ltab = P->ltab.as<uint8_t>();
+    cp.n = (uint32_t)n;
+    cp.nQ = (uint32_t)P->nQ;
+    cp.n_inst = (uint32_t)P->n_inst;
+    cp.nax = P->nax;
+    cp.cstate = P->cstate.as<uint4>();
+    const uint64_t words = 2 * ceil_div(n, (uint64_t)kBlock * 8) * ScanStatusWords<uint64_t>::kWords;
+    DevBuf status, ticket;
+    status.alloc(words * 8, s);
+    ticket.alloc(16, s);
+    scan_launch<CompactStateProblem, 8>("compact_state", cp, n, status.as<uint64_t>(), words,
+                                        ticket.as<uint32_t>(), s);
+}
+
+// The DOM_AGG_LE bits valid for dimension m.
+uint32_t le_flags(int m) {
+    uint32_t f = 0;
+    for (int a = 0; a < m && a < 4; ++a) f |= DOM_AGG_LE(a);
+    return f;
+}
+
+// The basic variant expands every axis; the record key holds at most three
+// tree-node fields.
+void check_basic(int m, uint32_t flags) {
+    if ((flags & DOM_AGG_BASIC) && m > 3)
+        fail(DOM_AGG_EUNSUPPORTED, "the basic variant is provided for m <= 3 (m = %d)", m);
+}
+
 // Argument checks shared by dom_agg_plan and dom_agg_run (no HIP call).
 void check_plan_args(int m, dom_agg_dtype coord_dtype, const void *d_coords, const void *q_coords, int64_t n_inst,
                      const int64_t *d_offsets, const int64_t *q_offsets) {
@@ -1370,8 +1438,10 @@ std::unique_ptr<Plan> make_plan(int m, dom_agg_dtype coord_dtype, const void *d_
     auto P = std::make_unique<Plan>();
     P->device = dev;
     P->m = m;
-    P->nax = m - 1;
     P->flags = flags;
+    P->le_mask = (flags >> 8) & 0xfu;
+    P->basic = (flags & DOM_AGG_BASIC) != 0;
+    P->nax = P->basic ? m : m - 1;  // (after basic is known)
     P->n_inst = n_inst;
     P->nD = nD;
     P->nQ = nQ;
@@ -1403,6 +1473,7 @@ std::unique_ptr<Plan> make_plan(int m, dom_agg_dtype coord_dtype, const void *d_
         }
         sig_keys.reset();
         sig_slots.reset();
+        if (P->nax > 0 && !P->use_slots) build_compact_state(P.get(), s);
         const uint64_t tiles = ceil_div((uint64_t)std::max<int64_t>(P->E, 1), kBlock * 8);
         P->scan_words = tiles * 4;
         P->scan_status.alloc(P->scan_words * 8, s);
@@ -1474,8 +1545,9 @@ dom_agg_status dom_agg_plan(dom_agg_plan_t *plan, int m, dom_agg_dtype coord_dty
     return guarded([&] {
         if (!plan) fail(DOM_AGG_EINVAL, "plan is NULL");
         check_plan_args(m, coord_dtype, d_coords, q_coords, n_inst, d_offsets, q_offsets);
-        if (flags & ~(uint32_t)(DOM_AGG_RECOMPUTE | DOM_AGG_GRAPH | DOM_AGG_NO_TUNE))
+        if (flags & ~(uint32_t)(DOM_AGG_RECOMPUTE | DOM_AGG_GRAPH | DOM_AGG_NO_TUNE | DOM_AGG_BASIC | le_flags(m)))
             fail(DOM_AGG_EINVAL, "unknown flags 0x%x", flags);
+        check_basic(m, flags);
         auto P = make_plan(m, coord_dtype, d_coords, q_coords, n_inst, d_offsets, q_offsets, flags,
                            static_cast<hipStream_t>(stream), nullptr, DOM_AGG_F32, false);
         *plan = P.release();
@@ -1488,7 +1560,9 @@ dom_agg_status dom_agg_run(int m, dom_agg_dtype coord_dtype, const void *d_coord
                            void *stream) {
     return guarded([&] {
         check_plan_args(m, coord_dtype, d_coords, q_coords, n_inst, d_offsets, q_offsets);
-        if (flags & ~(uint32_t)DOM_AGG_NO_TUNE) fail(DOM_AGG_EINVAL, "unknown flags 0x%x", flags);
+        if (flags & ~(uint32_t)(DOM_AGG_NO_TUNE | DOM_AGG_BASIC | le_flags(m)))
+            fail(DOM_AGG_EINVAL, "unknown flags 0x%x", flags);
+        check_basic(m, flags);
         const int64_t nD = d_offsets[n_inst], nQ = q_offsets[n_inst];
         check_forward_args(op, weight_dtype, weights, out, nD, nQ);
         if (nQ == 0) return;
@@ -1574,7 +1648,7 @@ dom_agg_status dom_agg_plan_get_info(dom_agg_plan_t plan, dom_agg_plan_info *inf
         info->data_records = plan->E_D;
         info->m = plan->m;
         info->key_bits = plan->key_bits;
-        for (int a = 0; a < 3; ++a) info->L[a] = plan->Lmax[a];
+        for (int a = 0; a < 3; ++a) info->L[a] = plan->Lmax[a];  // (nax <= 3 axes)
         info->sort_passes = (int32_t)plan->rec_shifts.size();
         info->digit_bits = kRadixBits;
         info->sort_tile = plan->tune.record_sort_tile;
@@ -1586,6 +1660,8 @@ dom_agg_status dom_agg_plan_get_info(dom_agg_plan_t plan, dom_agg_plan_info *inf
         else
             info->sort_class_records[0] = plan->E;
         info->workspace_bytes = plan->workspace();
+        info->le_mask = plan->le_mask;
+        info->basic = plan->basic ? 1 : 0;
     });
 }
 

@@ -35,14 +35,26 @@ __device__ __forceinline__ uint32_t ordered_key(int32_t x) { return (uint32_t)x 
 __device__ __forceinline__ bool is_nan(float x) { return x != x; }
 __device__ __forceinline__ bool is_nan(int32_t) { return false; }
 
-// keys[s] = (instance << 32 | ordered coordinate) or the ordered coordinate;
-// vals[s] = the point's internal slot, ppos[s] (or s while ppos is not yet
-// known).  Fused histogram of `passes` digits; NaN raises *nan_flag.
+// The point a list position holds before a coordinate sort: slot p (queries
+// first), or with data_first the data points first (slot nQ + p for p < nD),
+// so that a stable sort puts data before queries on equal coordinates (the
+// tie rule of <= on the last axis).
+__device__ __forceinline__ uint32_t slot_at(uint64_t p, uint32_t nQ, uint32_t n, bool data_first) {
+    if (!data_first) return (uint32_t)p;
+    const uint32_t nD = n - nQ;
+    return p < nD ? nQ + (uint32_t)p : (uint32_t)p - nD;
+}
+
+// keys[p] = (instance << 32 | ordered coordinate) or the ordered coordinate
+// of the point s at position p (slot_at); vals[p] = its internal slot,
+// ppos[s] (or s while ppos is not yet known).  Fused histogram of `passes`
+// digits; NaN raises *nan_flag.
 template <class K, class C, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void extract_keys_kernel(
     const C *__restrict__ q, const C *__restrict__ d, int m, int axis, uint32_t nQ, uint32_t n,
     const uint32_t *__restrict__ inst_of_slot, const uint32_t *__restrict__ ppos, K *__restrict__ keys,
-    uint32_t *__restrict__ vals, int passes, uint32_t *__restrict__ hist_part, uint32_t *__restrict__ nan_flag) {
+    uint32_t *__restrict__ vals, int passes, uint32_t *__restrict__ hist_part, uint32_t *__restrict__ nan_flag,
+    bool data_first) {
     __shared__ uint32_t s_hist[kMaxPasses * kRadix];
     for (int i = threadIdx.x; i < passes * kRadix; i += BLOCK) s_hist[i] = 0;
     __syncthreads();
@@ -56,24 +68,24 @@ __global__ __launch_bounds__(BLOCK) void extract_keys_kernel(
         uint32_t ps[U], is[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const uint64_t s0 = b + (uint64_t)u * BLOCK + threadIdx.x;
-            const uint64_t s = s0 < n ? s0 : (uint64_t)n - 1;
+            const uint64_t p0 = b + (uint64_t)u * BLOCK + threadIdx.x;
+            const uint64_t s = slot_at(p0 < n ? p0 : (uint64_t)n - 1, nQ, n, data_first);
             xs[u] = (s < nQ) ? q[s * m + axis] : d[(s - nQ) * m + axis];
             ps[u] = ppos ? ppos[s] : (uint32_t)s;
             is[u] = (sizeof(K) == 8 && inst_of_slot) ? inst_of_slot[s] : 0u;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const uint64_t s = b + (uint64_t)u * BLOCK + threadIdx.x;
-            const bool valid = s < n;
+            const uint64_t p = b + (uint64_t)u * BLOCK + threadIdx.x;
+            const bool valid = p < n;
             K key = 0;
             if (valid) {
                 const C x = xs[u];
                 saw_nan |= is_nan(x);
                 key = (K)ordered_key(x);
                 if constexpr (sizeof(K) == 8) key |= (K)is[u] << 32;
-                keys[s] = key;
-                vals[s] = ps[u];
+                keys[p] = key;
+                vals[p] = ps[u];
             }
             // (the low digits of coordinate keys are spread; the top one, with
             // the sign and exponent, and the instance digits are skewed)
@@ -98,7 +110,7 @@ __global__ __launch_bounds__(BLOCK) void extract_sigma_kernel(
     const C *__restrict__ q, const C *__restrict__ d, int axis, uint32_t nQ, uint32_t n,
     const uint32_t *__restrict__ inst_of_slot, const uint64_t *__restrict__ pr, const W *__restrict__ w,
     bool carry_weights, K *__restrict__ keys, uint64_t *__restrict__ vals, int passes,
-    uint32_t *__restrict__ hist_part, uint32_t *__restrict__ nan_flag) {
+    uint32_t *__restrict__ hist_part, uint32_t *__restrict__ nan_flag, bool data_first) {
     __shared__ uint32_t s_hist[kMaxPasses * kRadix];
     for (int i = threadIdx.x; i < passes * kRadix; i += BLOCK) s_hist[i] = 0;
     __syncthreads();
@@ -110,11 +122,12 @@ __global__ __launch_bounds__(BLOCK) void extract_sigma_kernel(
     for (uint64_t b = (uint64_t)blockIdx.x * BLOCK * U; b < n; b += stride) {
         C xs[U];
         uint64_t rss[U];
-        uint32_t wbs[U], is[U];
+        uint32_t wbs[U], is[U], ss[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const uint64_t s0 = b + (uint64_t)u * BLOCK + threadIdx.x;
-            const uint64_t s = s0 < n ? s0 : (uint64_t)n - 1;
+            const uint64_t p0 = b + (uint64_t)u * BLOCK + threadIdx.x;
+            const uint64_t s = slot_at(p0 < n ? p0 : (uint64_t)n - 1, nQ, n, data_first);
+            ss[u] = (uint32_t)s;
             xs[u] = (s < nQ) ? q[s * 2 + axis] : d[(s - nQ) * 2 + axis];
             rss[u] = pr[s];
             // (weights exist only with data: n > nQ, so the clamped index is in bounds)
@@ -124,11 +137,11 @@ __global__ __launch_bounds__(BLOCK) void extract_sigma_kernel(
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const uint64_t s = b + (uint64_t)u * BLOCK + threadIdx.x;
-            const bool valid = s < n;
+            const uint64_t p = b + (uint64_t)u * BLOCK + threadIdx.x;
+            const bool valid = p < n;
             K key = 0;
             if (valid) {
-                const bool isq = s < nQ;
+                const bool isq = ss[u] < nQ;
                 const C x = xs[u];
                 saw_nan |= is_nan(x);
                 key = (K)ordered_key(x);
@@ -143,8 +156,8 @@ __global__ __launch_bounds__(BLOCK) void extract_sigma_kernel(
                 } else {
                     payload = sp - nQ;
                 }
-                keys[s] = key;
-                vals[s] = ((uint64_t)((isq ? 0x80000000u : 0u) | r) << 32) | payload;
+                keys[p] = key;
+                vals[p] = ((uint64_t)((isq ? 0x80000000u : 0u) | r) << 32) | payload;
             }
             // (the low digits of coordinate keys are spread; the top one, with
             // the sign and exponent, and the instance digits are skewed)
@@ -154,6 +167,25 @@ __global__ __launch_bounds__(BLOCK) void extract_sigma_kernel(
     if (saw_nan) atomicOr(nan_flag, 1u);
     __syncthreads();
     hist_flush(s_hist, hist_part, passes);
+}
+
+// The basic variant (Sec. 4): every axis is expanded, and inside a tuple's
+// run of records data precede queries.  The point order the flat map follows
+// is then data first, then queries (slot order otherwise), with no
+// coordinate read: keys[p] = the instance (64-bit keys) or 0, slots[p] = the
+// internal slot of the point at position p.
+template <class K>
+__global__ void basic_order_kernel(uint32_t nQ, uint32_t n, const uint32_t *__restrict__ inst_of_slot,
+                                   const uint32_t *__restrict__ ppos, K *__restrict__ keys,
+                                   uint32_t *__restrict__ slots) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
+        const uint32_t s = slot_at(p, nQ, n, true);
+        K key = 0;
+        if constexpr (sizeof(K) == 8) key = inst_of_slot ? (K)inst_of_slot[s] << 32 : K(0);
+        keys[p] = key;
+        slots[p] = ppos[s];
+    }
 }
 
 // inst_of_slot[s]: the instance owning slot s (largest k with off[k] <= row).
@@ -227,6 +259,9 @@ struct RankProblem {
     uint64_t *pr;                // or [n] by input slot: rank << 32 | internal slot (m = 2)
     uint32_t *cdf_d, *cdf_q;     // or null; one instance: data / queries of rank below r, at [r]
     uint32_t *dinv, *qinv;       // [nD], [nQ]: input row of each position
+    // <= on this axis: the queries' ranks move up by one (slots below nq_le
+    // are queries; 0 for strict dominance)
+    uint32_t nq_le;
 
     __device__ static uint32_t inst(const Raw &r) {
         if constexpr (sizeof(K) == 8) return (uint32_t)(r.key >> 32);
@@ -269,22 +304,27 @@ struct RankProblem {
                 qinv[p] = cur.slot;
                 sp = p;
             }
-            if (pr) pr[cur.slot] = ((uint64_t)r << 32) | sp;
+            const uint32_t rq = r + (cur.slot < nq_le ? 1u : 0u);
+            if (pr) pr[cur.slot] = ((uint64_t)rq << 32) | sp;
             else ppos[cur.slot] = sp;
-            rank[sp] = r;
+            rank[sp] = rq;
         } else {
-            rank[cur.slot] = r;
+            rank[cur.slot] = r + (cur.slot < nq_le ? 1u : 0u);
         }
         if (last) kcount[ins] = (uint32_t)incl;
     }
 };
 
-// dst[p] = src[idx[p]]: inputs into internal order.
+// dst[p] = src[idx[p]]: inputs into internal order (idx is a permutation of
+// [0, n); an index outside it would mean a wrong sort and reads 0 instead).
 template <class T>
 __global__ void gather_kernel(const T *__restrict__ src, const uint32_t *__restrict__ idx, T *__restrict__ dst,
                               uint64_t n) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) dst[p] = src[idx[p]];
+    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
+        const uint32_t i = idx[p];
+        dst[p] = i < n ? src[i] : T(0);
+    }
 }
 
 // Records that carry their weights: rw[s] = rank of the first axis (low
@@ -298,17 +338,24 @@ __global__ void pack_rank_weight_kernel(const uint32_t *__restrict__ rank0, cons
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += stride) {
         uint32_t wb = 0;
-        if (w && s >= nQ) __builtin_memcpy(&wb, &w[dinv[s - nQ]], 4);
+        if (w && s >= nQ) {
+            const uint32_t row = dinv[s - nQ];
+            if (row < n - nQ) __builtin_memcpy(&wb, &w[row], 4);  // (dinv is a permutation of the data rows)
+        }
         rw[s] = (uint64_t)rank0[s] | ((uint64_t)wb << 32);
     }
 }
 
-// dst[idx[p]] = src[p]: results back into input order.
+// dst[idx[p]] = src[p]: results back into input order (idx is a permutation
+// of [0, n); an index outside it is dropped).
 template <class T>
 __global__ void scatter_kernel(const T *__restrict__ src, const uint32_t *__restrict__ idx, T *__restrict__ dst,
                                uint64_t n) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) dst[idx[p]] = src[p];
+    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
+        const uint32_t i = idx[p];
+        if (i < n) dst[i] = src[p];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1226,14 +1273,23 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(EmitArgs a, K *__restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Regrouping (Sec. 4: the sort by ID and the scan tagged by ID).  A record's
-// slot is its tuple of tree levels (j_1, ..., j_{m-1}), read off the key (the
-// level of node (1 << j) | prefix is its highest set bit), in mixed radix over
-// the per-axis field widths.  A query has at most one record per slot, and
-// one exactly when every j_a is a 1-digit of its axis-a rank (a 0-digit for
-// data).  So the scan can store each partial at part[slot][row] with a plain
-// store, and a second pass folds each row's valid slots in slot order -- no
-// atomics, and the same fold order on every run.
+// Regrouping (Sec. 4: the sort by ID and the scan tagged by ID).  Every
+// partial aggregate of a point goes to a place of its own that depends only
+// on the point and on the record's tuple of tree levels (j_1, ..., j_{m-1}),
+// read off the key (the level of node (1 << j) | prefix is its highest set
+// bit): a point has at most one record per level tuple, and one exactly when
+// every j_a is a 1-digit of its axis-a rank (a query) or a 0-digit (a data
+// point).  The scan stores each partial with a plain store, and a second pass
+// folds each point's partials in level-tuple order -- no atomics, and the
+// same fold order on every run.  Two layouts of those places:
+//   slot mode     part[slot][row], slot = the level tuple in mixed radix over
+//                 the per-axis field widths (all tuples, valid or not): no
+//                 per-point state is read while scanning;
+//   compact mode  part[base(row) + t], t = the record's index among the
+//                 point's records (the valid tuples in the same order), base
+//                 = exclusive sum of the record counts of the rows before it:
+//                 exactly one place per record, for wide tables that would be
+//                 mostly empty (m = 4 with wide ranks).
 
 struct SlotMap {
     int nax;
@@ -1242,18 +1298,52 @@ struct SlotMap {
     uint32_t radix[3];
     uint32_t n_slots;  // product of the radices; stores to slots beyond it are dropped
     template <class K>
+    __device__ __forceinline__ uint32_t level(K key, int a) const {
+        const uint32_t node = (uint32_t)(key >> field_shift[a]) & field_mask[a];
+        return 31u - (uint32_t)__clz(node);
+    }
+    template <class K>
     __device__ __forceinline__ uint32_t slot(K key) const {
         uint32_t sl = 0;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            if (a < nax) {
-                const uint32_t node = (uint32_t)(key >> field_shift[a]) & field_mask[a];
-                sl = sl * radix[a] + (31u - (uint32_t)__clz(node));
-            }
-        }
+        for (int a = 0; a < 3; ++a)
+            if (a < nax) sl = sl * radix[a] + level(key, a);
         return sl;
     }
+    // Compact mode.  st = {base, fa_1, fa_2, fa_3} of the record's point:
+    // fa_a holds the digits of the axis-a rank that select prefixes (1-digits
+    // for a query, 0-digits for a data point), left-aligned (digit j at bit
+    // 31 - j).  On axis a the record is the t_a-th selected digit from the top
+    // (t_a = selected digits above its level); the point's records are
+    // numbered in mixed radix over the per-axis counts, first axis slowest,
+    // which is the order of the flat map's walk and of the level tuples.
+    template <class K>
+    __device__ __forceinline__ uint64_t compact(K key, const uint4 &st) const {
+        const uint32_t fa[3] = {st.y, st.z, st.w};
+        uint32_t t = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (a < nax) {
+                const uint32_t j = level(key, a);
+                const uint32_t c = (uint32_t)__popc(fa[a]);
+                const uint32_t ta = j ? (uint32_t)__popc(fa[a] >> (32u - j)) : 0u;
+                t = t * c + ta;
+            }
+        }
+        return (uint64_t)st.x + t;
+    }
 };
+
+// Records per point of the compact layout: product over axes of the
+// selected digits.
+__device__ __forceinline__ uint32_t compact_count(const uint4 &st, int nax) {
+    uint32_t c = 1;
+    const uint32_t fa[3] = {st.y, st.z, st.w};
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        if (a < nax) c *= (uint32_t)__popc(fa[a]);
+    return c;
+}
 
 enum { OP_SUM = 0, OP_MAX = 1, OP_COUNT = 2 };
 
@@ -1264,15 +1354,65 @@ template <> __device__ __forceinline__ int64_t lowest<int64_t>() { return INT64_
 template <> __device__ __forceinline__ float lowest<float>() { return -__builtin_inff(); }
 template <> __device__ __forceinline__ double lowest<double>() { return -__builtin_inf(); }
 
-template <class V, int OP>
+// The value F is accumulated in: the output type, except fp32 sums, which
+// carry a compensated pair (F32c) through the scans and the fold.
+template <class Out, int OP>
+struct AccumOf {
+    using type = Out;
+};
+template <>
+struct AccumOf<float, OP_SUM> {
+    using type = F32c;
+};
+
+template <class A, int OP>
 struct Monoid {
-    __device__ static V identity() {
-        if constexpr (OP == OP_MAX) return lowest<V>();
-        else return V(0);
+    __device__ static A identity() {
+        if constexpr (OP == OP_MAX) return lowest<A>();
+        else return A(0);
     }
-    __device__ static V combine(V a, V b) {
+    __device__ static A combine(A a, A b) {
         if constexpr (OP == OP_MAX) return b > a ? b : a;
         else return a + b;
+    }
+};
+template <>
+struct Monoid<F32c, OP_SUM> {
+    __device__ static F32c identity() { return F32c{0.0f, 0.0f}; }
+    __device__ static F32c combine(F32c a, F32c b) { return f32c_add(a, b); }
+};
+
+template <class A, class X>
+__device__ __forceinline__ A acc_from(X x) {
+    if constexpr (std::is_same<A, F32c>::value) return F32c{(float)x, 0.0f};
+    else return A(x);
+}
+template <class Out, class A>
+__device__ __forceinline__ Out acc_out(A a) {
+    if constexpr (std::is_same<A, F32c>::value) return (Out)(a.hi + a.lo);
+    else return (Out)a;
+}
+
+// Where a scan puts the partial aggregates of one kind of point (queries in
+// the forward, data in the backward; both in the forward that also reports
+// data totals).  part == null: not stored.
+template <class Out>
+struct PartDest {
+    Out *part;
+    const uint4 *cstate;  // compact mode: [rows] state of the rows, or null (slot mode)
+    uint64_t stride;      // rows (slot mode)
+    uint64_t cap;         // entries of part: stores at or beyond it are dropped
+    template <class K, class A>
+    __device__ __forceinline__ void store(const SlotMap &sm, K key, uint32_t row, A v) const {
+        if (!part || row >= stride) return;  // (rows are below stride by construction)
+        uint64_t at;
+        if (cstate) {
+            at = sm.compact(key, cstate[row]);
+        } else {
+            const uint32_t sl = sm.slot(key);
+            at = (uint64_t)sl * stride + row;
+        }
+        if (at < cap) part[at] = acc_out<Out>(v);
     }
 };
 
@@ -1281,16 +1421,17 @@ struct Monoid {
 // carry the unit e; at a query record the scan value is F over the data
 // records before it in its segment, i.e. over the data points that share
 // this tuple and lie strictly below it on the last axis.  Each such partial
-// goes to part[slot * nQ + query] (slot mode) or is F-combined atomically
-// into out[query] (atomic mode, for very sparse slot tables).  Payloads and
-// w use the internal numbering of the points.
+// goes to its place of the regrouping (q); with dq.part set, the inclusive
+// value at every data record goes to its place too (the partial aggregates
+// the construction also carries at data records).  Payloads and w use the
+// internal numbering of the points.
 //
 // INL: the records carry the weights (a data record's payload is its weight
 // bits, a query record's key has bit flag_shift set and its payload is the
 // query's row), so the scan reads them in sequence instead of gathering.
-template <class K, class W, class Acc, int OP, bool INL = false>
+template <class K, class W, class Out, int OP, bool INL = false>
 struct ForwardProblem {
-    using V = Acc;
+    using V = typename AccumOf<Out, OP>::type;
     struct Raw {
         K key;
         uint32_t payload;
@@ -1298,9 +1439,7 @@ struct ForwardProblem {
     const K *keys;
     const uint32_t *vals;
     const W *w;  // unused for COUNT and INL
-    V *out;      // atomic mode target
-    V *part;     // slot mode target, or null
-    uint64_t stride;
+    PartDest<Out> q, d;
     uint64_t nw;     // weights (|D|): payloads are checked against it
     SlotMap sm;
     int flag_shift;  // INL
@@ -1324,21 +1463,16 @@ struct ForwardProblem {
             static_assert(sizeof(W) == 4, "");
             W x;
             __builtin_memcpy(&x, &cur.payload, 4);
-            return V(x);
+            return acc_from<V>(x);
         } else {
-            return cur.payload < nw ? V(w[cur.payload]) : identity();  // (always below |D|)
+            return cur.payload < nw ? acc_from<V>(w[cur.payload]) : identity();  // (always below |D|)
         }
     }
     __device__ void emit(uint64_t, const Raw &cur, V, V, V incl, bool) const {
-        if (!is_query(cur)) return;
-        const uint32_t q = INL ? cur.payload : (cur.payload & ~kQueryFlag);
-        if (q >= stride) return;  // (rows are < stride = |Q| by construction)
-        if (part) {
-            const uint32_t sl = sm.slot(cur.key);
-            if (sl < sm.n_slots) part[(uint64_t)sl * stride + q] = incl;
-        } else if (incl != identity()) {
-            if constexpr (OP == OP_MAX) atomic_max(out + q, incl);
-            else atomic_sum(out + q, incl);
+        if (is_query(cur)) {
+            q.store(sm, cur.key, INL ? cur.payload : (cur.payload & ~kQueryFlag), incl);
+        } else if constexpr (!INL) {
+            d.store(sm, cur.key, cur.payload, incl);
         }
     }
 };
@@ -1348,11 +1482,11 @@ struct ForwardProblem {
 // grad_out over the queries after it in its segment, i.e. the queries sharing
 // the tuple and lying strictly above it on the last axis (equal last
 // coordinates put queries first, so they come before the data record and are
-// not counted).  Those partials go to part[slot * nD + data position], or
-// are summed atomically into grad[data position] (internal numbering).
+// not counted).  Those partials go to the data point's places of the
+// regrouping (internal numbering).
 template <class K, class G>
 struct BackwardProblem {
-    using V = G;
+    using V = typename AccumOf<G, OP_SUM>::type;
     struct Raw {
         K key;
         uint32_t payload;
@@ -1360,46 +1494,38 @@ struct BackwardProblem {
     const K *keys;
     const uint32_t *vals;
     const G *g;
-    G *grad;
-    G *part;
-    uint64_t stride;
+    PartDest<G> d;
     uint64_t ng;  // |Q|
     SlotMap sm;
     uint64_t E;
 
-    __device__ G identity() const { return G(0); }
-    __device__ G combine(G a, G b) const { return a + b; }
+    __device__ V identity() const { return Monoid<V, OP_SUM>::identity(); }
+    __device__ V combine(V a, V b) const { return Monoid<V, OP_SUM>::combine(a, b); }
     __device__ Raw load(uint64_t i) const {
         const uint64_t q = E - 1 - i;
         return Raw{keys[q], vals[q]};
     }
     __device__ bool head(const Raw &prev, const Raw &cur) const { return prev.key != cur.key; }
-    __device__ G value(const Raw &, bool, const Raw &cur, uint64_t) const {
-        if (!(cur.payload & kQueryFlag)) return G(0);
+    __device__ V value(const Raw &, bool, const Raw &cur, uint64_t) const {
+        if (!(cur.payload & kQueryFlag)) return identity();
         const uint32_t q = cur.payload & ~kQueryFlag;
-        return q < ng ? g[q] : G(0);  // (always below |Q|)
+        return q < ng ? acc_from<V>(g[q]) : identity();  // (always below |Q|)
     }
-    __device__ void emit(uint64_t, const Raw &cur, G, G excl, G, bool) const {
+    __device__ void emit(uint64_t, const Raw &cur, V, V excl, V, bool) const {
         if (cur.payload & kQueryFlag) return;
-        if (cur.payload >= stride) return;  // (rows are < stride = |D| by construction)
-        if (part) {
-            const uint32_t sl = sm.slot(cur.key);
-            if (sl < sm.n_slots) part[(uint64_t)sl * stride + cur.payload] = excl;
-        } else if (excl != G(0)) {
-            atomic_sum(grad + cur.payload, excl);
-        }
+        d.store(sm, cur.key, cur.payload, excl);
     }
 };
 
-// Folds each row's valid slots in slot order: out[o] = F over part[slot][o].
-// Row o is point slot_base + o; its valid slots are the level tuples whose
-// digits of the point's ranks equal `digit` (1 for queries, 0 for data) and
-// lie below the instance's widths.
+// Folds each row's partials in level-tuple order: out[inv[o]] = F over the
+// partials of row o (point slot_base + o).
 struct RegroupArgs {
     const uint32_t *inv;           // [nout]: output index of row o, or null (identity)
-    const uint32_t *rank;          // [nax][n] by point slot
-    const uint32_t *inst_of_slot;  // [n] or null
-    const uint8_t *ltab;           // [nax][n_inst]
+    const uint32_t *rank;          // [nax][n] by point slot (slot mode)
+    const uint32_t *inst_of_slot;  // [n] or null (slot mode)
+    const uint8_t *ltab;           // [nax][n_inst] (slot mode)
+    const uint4 *cstate;           // [nout] state of the rows (compact mode)
+    uint64_t cap;                  // entries of the compact table
     uint32_t n, n_inst;
     uint32_t slot_base;
     uint32_t digit;
@@ -1407,9 +1533,13 @@ struct RegroupArgs {
     uint64_t nout;
 };
 
-template <class V, int OP, int NAX>
-__global__ __launch_bounds__(256) void regroup_kernel(RegroupArgs a, const V *__restrict__ part,
-                                                      V *__restrict__ out) {
+// Slot mode: a row's valid slots are the level tuples whose digits of the
+// point's ranks equal `digit` (1 for queries, 0 for data) and lie below the
+// instance's widths.
+template <class Out, int OP, int NAX>
+__global__ __launch_bounds__(256) void regroup_kernel(RegroupArgs a, const Out *__restrict__ part,
+                                                      Out *__restrict__ out) {
+    using A = typename AccumOf<Out, OP>::type;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t o = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; o < a.nout; o += stride) {
         const uint32_t s = a.slot_base + (uint32_t)o;
@@ -1418,21 +1548,22 @@ __global__ __launch_bounds__(256) void regroup_kernel(RegroupArgs a, const V *__
 #pragma unroll
         for (int ax = 0; ax < NAX; ++ax) {
             const uint32_t r = a.rank[(uint64_t)ax * a.n + s];
-            L[ax] = a.ltab[(uint64_t)ax * a.n_inst + ins];
+            L[ax] = a.ltab[(uint64_t)ax * a.n_inst + (ins < a.n_inst ? ins : 0u)];
             x[ax] = a.digit ? r : ~r;
         }
         // digit j of the L-digit string x, counted from the top, is bit L-1-j
         auto ok = [&](int ax, uint32_t j) { return j < L[ax] && ((x[ax] >> (L[ax] - 1u - j)) & 1u); };
-        V acc = Monoid<V, OP>::identity();
+        A acc = Monoid<A, OP>::identity();
+        auto add = [&](Out v) { acc = Monoid<A, OP>::combine(acc, acc_from<A>(v)); };
         if constexpr (NAX == 0) {
-            acc = part[o];
+            add(part[o]);
         } else if constexpr (NAX == 1) {
             // 8 slots per round, loaded before any is folded (row indices
             // clamped below radix), folded in slot order as above
             constexpr uint32_t kU = 8;
             const uint32_t R = a.radix[0];
             for (uint32_t j0 = 0; j0 < R; j0 += kU) {
-                V v[kU];
+                Out v[kU];
 #pragma unroll
                 for (uint32_t u = 0; u < kU; ++u) {
                     const uint32_t j = (j0 + u < R) ? j0 + u : R - 1;
@@ -1440,14 +1571,13 @@ __global__ __launch_bounds__(256) void regroup_kernel(RegroupArgs a, const V *__
                 }
 #pragma unroll
                 for (uint32_t u = 0; u < kU; ++u)
-                    if (j0 + u < R && ok(0, j0 + u)) acc = Monoid<V, OP>::combine(acc, v[u]);
+                    if (j0 + u < R && ok(0, j0 + u)) add(v[u]);
             }
         } else if constexpr (NAX == 2) {
             for (uint32_t j0 = 0; j0 < a.radix[0]; ++j0) {
                 const bool v0 = ok(0, j0);
                 for (uint32_t j1 = 0; j1 < a.radix[1]; ++j1)
-                    if (v0 && ok(1, j1))
-                        acc = Monoid<V, OP>::combine(acc, part[((uint64_t)j0 * a.radix[1] + j1) * a.nout + o]);
+                    if (v0 && ok(1, j1)) add(part[((uint64_t)j0 * a.radix[1] + j1) * a.nout + o]);
             }
         } else {
             for (uint32_t j0 = 0; j0 < a.radix[0]; ++j0) {
@@ -1456,13 +1586,88 @@ __global__ __launch_bounds__(256) void regroup_kernel(RegroupArgs a, const V *__
                     const bool v1 = v0 && ok(1, j1);
                     for (uint32_t j2 = 0; j2 < a.radix[2]; ++j2)
                         if (v1 && ok(2, j2))
-                            acc = Monoid<V, OP>::combine(
-                                acc, part[(((uint64_t)j0 * a.radix[1] + j1) * a.radix[2] + j2) * a.nout + o]);
+                            add(part[(((uint64_t)j0 * a.radix[1] + j1) * a.radix[2] + j2) * a.nout + o]);
                 }
             }
         }
-        out[a.inv ? a.inv[o] : o] = acc;
+        const uint64_t dst = a.inv ? (uint64_t)a.inv[o] : o;
+        if (dst < a.nout) out[dst] = acc_out<Out>(acc);  // (inv is a permutation of the rows)
     }
 }
+
+// Compact mode: row o's partials are part[base, base + count) in level-tuple
+// order.  Each thread folds one row; a wavefront's rows hold consecutive
+// runs of the table.
+template <class Out, int OP>
+__global__ __launch_bounds__(256) void regroup_compact_kernel(RegroupArgs a, int nax, const Out *__restrict__ part,
+                                                              Out *__restrict__ out) {
+    using A = typename AccumOf<Out, OP>::type;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t o = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; o < a.nout; o += stride) {
+        const uint4 st = a.cstate[o];
+        const uint32_t cnt = compact_count(st, nax);
+        A acc = Monoid<A, OP>::identity();
+        uint64_t i = st.x, end = (uint64_t)st.x + cnt;
+        if (end > a.cap) end = a.cap;  // (counts add up to the table size by construction)
+        // 4 partials per round, loaded before any is folded
+        for (; i + 4 <= end; i += 4) {
+            Out v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = part[i + u];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc = Monoid<A, OP>::combine(acc, acc_from<A>(v[u]));
+        }
+        for (; i < end; ++i) acc = Monoid<A, OP>::combine(acc, acc_from<A>(part[i]));
+        const uint64_t dst = a.inv ? (uint64_t)a.inv[o] : o;
+        if (dst < a.nout) out[dst] = acc_out<Out>(acc);  // (inv is a permutation of the rows)
+    }
+}
+
+// State of the compact layout for every point slot: {base, fa_1, fa_2, fa_3}
+// (see SlotMap::compact), base = exclusive sum of the record counts of the
+// slots before it of the same kind (queries: slots < nQ; data: the rest), as a
+// segmented scan restarted at slot nQ.  fa_a = the selecting digits of the
+// axis-a rank, left-aligned: a query selects its 1-digits, a data point its
+// 0-digits (Lemma 2's prefix sets P1 and P0), over the L_a digits of its
+// instance.
+struct CompactStateProblem {
+    using V = uint64_t;
+    using Raw = uint32_t;
+    const uint32_t *rank;          // [nax][n] by slot
+    const uint32_t *inst_of_slot;  // [n] or null
+    const uint8_t *ltab;           // [nax][n_inst]
+    uint32_t n, nQ, n_inst;
+    int nax;
+    uint4 *cstate;                 // [n]
+
+    __device__ uint4 state(uint32_t s) const {
+        const uint32_t ins = inst_of_slot ? inst_of_slot[s] : 0u;
+        const bool isq = s < nQ;
+        uint32_t fa[3] = {0, 0, 0};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (a < nax) {
+                const uint32_t L = ltab[(uint64_t)a * n_inst + (ins < n_inst ? ins : 0u)];
+                const uint32_t r = rank[(uint64_t)a * n + s];
+                const uint32_t mask = L >= 32u ? 0xffffffffu : ((1u << L) - 1u);
+                const uint32_t full = (isq ? r : ~r) & mask;
+                fa[a] = L ? full << (32u - L) : 0u;
+            }
+        }
+        return make_uint4(0u, fa[0], fa[1], fa[2]);
+    }
+    __device__ V identity() const { return 0ull; }
+    __device__ V combine(V a, V b) const { return a + b; }
+    __device__ Raw load(uint64_t i) const { return (uint32_t)i; }
+    __device__ bool head(const Raw &, const Raw &cur) const { return cur == nQ; }
+    __device__ V value(const Raw &, bool, const Raw &cur, uint64_t) const {
+        return compact_count(state(cur), nax);
+    }
+    __device__ void emit(uint64_t, const Raw &cur, V, V excl, V, bool) const {
+        uint4 st = state(cur);
+        st.x = (uint32_t)excl;
+        cstate[cur] = st;
+    }
+};
 
 }  // namespace domagg

@@ -121,10 +121,13 @@ class DomAggPlan:
     independent instances (rows of instance k: offsets[k] .. offsets[k+1]-1).
     recompute: keep only per-point state and rebuild the records on each
     forward/backward.  graph: replay forward/backward from a HIP graph.
+    le_mask: bit a asks for d_a <= q_a on axis a instead of d_a < q_a.
+    basic: the basic construction of Sec. 4 (every axis expanded; m <= 3).
     """
 
     def __init__(self, d: torch.Tensor, q: torch.Tensor, d_offsets=None, q_offsets=None,
-                 recompute: bool = False, graph: bool = False, tune: bool = True):
+                 recompute: bool = False, graph: bool = False, tune: bool = True, le_mask: int = 0,
+                 basic: bool = False):
         lib = _lib()
         d = _coords(d, "d")
         q = _coords(q, "q")
@@ -135,7 +138,8 @@ class DomAggPlan:
         self.device = d.device
         doff, qoff = _offsets(self.nD, self.nQ, d_offsets, q_offsets)
         self.n_inst = int(doff.size - 1)
-        flags = (B.RECOMPUTE if recompute else 0) | (B.GRAPH if graph else 0) | (0 if tune else B.NO_TUNE)
+        flags = ((B.RECOMPUTE if recompute else 0) | (B.GRAPH if graph else 0) | (0 if tune else B.NO_TUNE)
+                 | (B.BASIC if basic else 0) | _le_flags(le_mask))
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             B.check(lib.dom_agg_plan(ctypes.byref(h), self.m, _TORCH_TO_DT[d.dtype], _ptr(d), _ptr(q),
@@ -193,8 +197,13 @@ class DomAggFunction(torch.autograd.Function):
         return ctx.plan.backward(grad_out.to(ctx.wdtype)), None
 
 
+def _le_flags(le_mask: int) -> int:
+    return sum(B.LE(a) for a in range(4) if (int(le_mask) >> a) & 1)
+
+
 def dom_agg_run(d: torch.Tensor, q: torch.Tensor, w: torch.Tensor | None = None, op: str = "sum",
-                d_offsets=None, q_offsets=None, out: torch.Tensor | None = None, tune: bool = True):
+                d_offsets=None, q_offsets=None, out: torch.Tensor | None = None, tune: bool = True,
+                le_mask: int = 0, basic: bool = False):
     """One-shot forward (no plan is kept; the records carry the weights)."""
     lib = _lib()
     d = _coords(d, "d")
@@ -209,7 +218,8 @@ def dom_agg_run(d: torch.Tensor, q: torch.Tensor, w: torch.Tensor | None = None,
         B.check(lib.dom_agg_run(int(d.shape[1]), _TORCH_TO_DT[d.dtype], _ptr(d), _ptr(q), int(doff.size - 1),
                                 doff.ctypes.data_as(ctypes.c_void_p), qoff.ctypes.data_as(ctypes.c_void_p),
                                 B.OPS[op], _TORCH_TO_DT.get(wdt, B.I64), _ptr(w) if op != "count" else None,
-                                _ptr(out), 0 if tune else B.NO_TUNE, _stream()))
+                                _ptr(out), (0 if tune else B.NO_TUNE) | (B.BASIC if basic else 0) | _le_flags(le_mask),
+                                _stream()))
     return out
 
 
@@ -223,8 +233,8 @@ def dom_agg(d: torch.Tensor, q: torch.Tensor, w: torch.Tensor | None = None, op:
     below it in every coordinate (e when none).  Differentiable in w for
     op="sum" with float weights (a plan is then kept for the backward);
     otherwise one one-shot call."""
-    if not _needs_grad(w, op) and not plan_kwargs:
-        return dom_agg_run(d, q, w, op)
+    if not _needs_grad(w, op) and not set(plan_kwargs) - {"le_mask", "basic"}:
+        return dom_agg_run(d, q, w, op, **plan_kwargs)
     plan = DomAggPlan(d, q, **plan_kwargs)
     if _needs_grad(w, op):
         return DomAggFunction.apply(w, plan)
@@ -233,8 +243,8 @@ def dom_agg(d: torch.Tensor, q: torch.Tensor, w: torch.Tensor | None = None, op:
 
 def dom_agg_batched(d, q, w, d_offsets, q_offsets, op: str = "sum", **plan_kwargs) -> torch.Tensor:
     """dom_agg over independent instances stacked along the rows."""
-    if not _needs_grad(w, op) and not plan_kwargs:
-        return dom_agg_run(d, q, w, op, d_offsets, q_offsets)
+    if not _needs_grad(w, op) and not set(plan_kwargs) - {"le_mask", "basic"}:
+        return dom_agg_run(d, q, w, op, d_offsets, q_offsets, **plan_kwargs)
     plan = DomAggPlan(d, q, d_offsets, q_offsets, **plan_kwargs)
     if _needs_grad(w, op):
         return DomAggFunction.apply(w, plan)

@@ -75,6 +75,10 @@ def _plan(B, m=2, dt=None, d=1, q=1, n_inst=1, doff=None, qoff=None, flags=0, nu
     (dict(d=0), "EINVAL"), (dict(q=0), "EINVAL"), (dict(flags=1), "EINVAL"), (dict(flags=64), "EINVAL"),
     (dict(doff=[0, 1 << 30], qoff=[0, 1 << 30]), "ETOOBIG"),
     (dict(n_inst=2, doff=[0, 3, 2], qoff=[0, 1, 3]), "EINVAL"),
+    (dict(m=2, flags=0x400), "EINVAL"),          # DOM_AGG_LE(2) with m = 2
+    (dict(m=1, flags=0x200), "EINVAL"),          # DOM_AGG_LE(1) with m = 1
+    (dict(m=4, flags=16), "EUNSUPPORTED"),        # DOM_AGG_BASIC with m = 4
+    (dict(m=4, flags=16 | 0x800), "EUNSUPPORTED"),
 ])
 def test_plan_argument_validation(B, kw, status):
     st, _ = _plan(B, **kw)
@@ -114,6 +118,7 @@ def _run(B, m=2, dt=None, d=1, q=1, n_inst=1, doff=None, qoff=None, op=0, wdt=No
     (dict(doff=[1, 4]), "EINVAL"), (dict(d=0), "EINVAL"), (dict(flags=2), "EINVAL"), (dict(flags=4), "EINVAL"),
     (dict(op=7), "EINVAL"), (dict(wdt=9), "EINVAL"), (dict(w=0), "EINVAL"), (dict(out=0), "EINVAL"),
     (dict(doff=[0, 1 << 30], qoff=[0, 1 << 30]), "ETOOBIG"),
+    (dict(m=2, flags=0x400), "EINVAL"), (dict(m=4, flags=16), "EUNSUPPORTED"),
 ])
 def test_run_argument_validation(B, kw, status):
     st = _run(B, **kw)
@@ -199,3 +204,14 @@ def test_no_kernel_uses_scratch_memory():
             kernels[cur] = int(m.group(2))
     assert kernels, "no resource remarks"
     assert not {k: v for k, v in kernels.items() if v}, "kernels with scratch"
+
+
+def test_le_and_basic_flags_pass_validation_without_device(B):
+    """Valid DOM_AGG_LE / DOM_AGG_BASIC flags get past validation: with no
+    device the call then reports ENODEV, not EINVAL."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    for m, flags in ((2, B.LE(0) | B.LE(1)), (3, B.BASIC | B.LE(2)), (1, B.BASIC)):
+        st, _ = _plan(B, m=m, flags=flags)
+        assert B.STATUS_NAMES[st] == "ENODEV", (m, flags)

@@ -233,22 +233,43 @@ def test_fp32_results_repeat_bit_for_bit():
     assert np.array_equal(q.forward(w, "sum").cpu().numpy(), a)
 
 
-def test_atomic_regroup_path_m4():
-    """Wide ranks in m = 4 make the slot table sparse: the plan falls back to
-    atomic F, which must give the same results."""
+def test_compact_regroup_path_m4():
+    """Wide ranks in m = 4 make the level-tuple table sparse: the plan uses
+    the compact table (one place per record), which must give the same
+    results, and fp32 sums that repeat bit for bit."""
     c = workloads.small_case(13, 4, 4000, 4000, alphabet=None, coord="f32", weight="int64")
     p = _plan(c)
     assert p.info()["regroup_slots"] == 0, p.info()
     want = oracle.construction(4, c.D, c.Q, c.w, "sum")
-    check_exact(p.forward(to_dev(c.w), "sum"), want, "atomic sum")
-    check_exact(p.forward(to_dev(c.w), "max"), oracle.construction(4, c.D, c.Q, c.w, "max"), "atomic max")
+    check_exact(p.forward(to_dev(c.w), "sum"), want, "compact sum")
+    check_exact(p.forward(to_dev(c.w), "max"), oracle.construction(4, c.D, c.Q, c.w, "max"), "compact max")
+    check_exact(p.forward(None, "count"), oracle.construction(4, c.D, c.Q, None, "count"), "compact count")
     wf = c.w.astype(np.float32)
     g = np.random.default_rng(9).standard_normal(c.Q.shape[0]).astype(np.float32)
     gw = p.backward(to_dev(g))
     check_fp(gw, oracle.transposed_sum(4, c.D, c.Q, g.astype(np.float64)),
-             oracle.transposed_sum(4, c.D, c.Q, np.abs(g.astype(np.float64))), "atomic grad")
-    check_fp(p.forward(to_dev(wf), "sum"), oracle.construction(4, c.D, c.Q, wf.astype(np.float64), "sum"),
-             oracle.construction(4, c.D, c.Q, np.abs(wf.astype(np.float64)), "sum"), "atomic f32 sum")
+             oracle.transposed_sum(4, c.D, c.Q, np.abs(g.astype(np.float64))), "compact grad")
+    fw = p.forward(to_dev(wf), "sum")
+    check_fp(fw, oracle.construction(4, c.D, c.Q, wf.astype(np.float64), "sum"),
+             oracle.construction(4, c.D, c.Q, np.abs(wf.astype(np.float64)), "sum"), "compact f32 sum")
+    a, ga = fw.cpu().numpy(), gw.cpu().numpy()
+    for _ in range(3):
+        assert np.array_equal(p.forward(to_dev(wf), "sum").cpu().numpy(), a)
+        assert np.array_equal(p.backward(to_dev(g)).cpu().numpy(), ga)
+
+
+def test_same_sign_fp32_weights_long_segments():
+    """All-positive fp32 weights over segments that span hundreds of scan
+    tiles: the error must stay within 2e-6 * sum |w| (compensated sums)."""
+    c = workloads.f32_uniform(2, 1 << 20, workloads.BASE_SEED + 41, "pos")
+    w = np.abs(c.w).astype(np.float32) + np.float32(0.5)
+    p = _plan(c)
+    w64 = w.astype(np.float64)
+    want = oracle.fenwick2(c.D, c.Q, w64, "sum")
+    check_fp(p.forward(to_dev(w), "sum"), want, want, "same-sign sum")
+    g = np.full(c.Q.shape[0], 0.75, dtype=np.float32)
+    gw = oracle.fenwick2(-c.Q.astype(np.float64), -c.D.astype(np.float64), g.astype(np.float64), "sum")
+    check_fp(p.backward(to_dev(g)), gw, gw, "same-sign grad")
 
 
 # ---------------------------------------------------------------------------
