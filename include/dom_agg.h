@@ -231,6 +231,28 @@ dom_agg_status dom_agg_run(int m, dom_agg_dtype coord_dtype, const void *d_coord
                            const int64_t *q_offsets, dom_agg_op op, dom_agg_dtype weight_dtype,
                            const void *weights, void *out, uint32_t flags, void *stream);
 
+/*
+ * dom_agg_run for callers that cannot allocate device memory: code being
+ * captured into a HIP graph, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, validation and results as dom_agg_run (flags
+ * as there; the autotuner is always off, as with DOM_AGG_NO_TUNE, so that
+ * results equal dom_agg_run's with that flag bit for bit).  Every workspace
+ * buffer of the call comes from one static device array of 256 MiB that the
+ * library holds on each GPU it runs on until the process ends; no hipMalloc,
+ * hipFree, pinned host allocation or allocator hook is called.  Problems whose
+ * workspace does not fit return DOM_AGG_ETOOBIG before writing out (roughly:
+ * m = 2 with |D| + |Q| up to about 2^20 uniform points; the size of the flat
+ * map decides).  Every call on one GPU uses the same array, which keeps the
+ * last call's contents: calls that overlap on one GPU (different streams or
+ * threads) race and must not be issued.  The call synchronises with the
+ * stream while it sizes the flat map, like dom_agg_run.
+ */
+dom_agg_status dom_agg_run_static(int m, dom_agg_dtype coord_dtype, const void *d_coords,
+                                  const void *q_coords, int64_t n_inst, const int64_t *d_offsets,
+                                  const int64_t *q_offsets, dom_agg_op op,
+                                  dom_agg_dtype weight_dtype, const void *weights, void *out,
+                                  uint32_t flags, void *stream);
+
 /* Sizes of a plan.  info (host) is filled on success. */
 dom_agg_status dom_agg_plan_get_info(dom_agg_plan_t plan, dom_agg_plan_info *info);
 

@@ -36,6 +36,7 @@ EXPORTS = (
     "dom_agg_forward",
     "dom_agg_backward",
     "dom_agg_run",
+    "dom_agg_run_static",
     "dom_agg_plan_get_info",
     "dom_agg_plan_destroy",
     "dom_agg_status_string",
@@ -113,6 +114,8 @@ def load(path: str | None = None):
     lib.dom_agg_backward.restype = I
     lib.dom_agg_run.argtypes = [I, I, P, P, I64, P, P, I, I, P, P, U32, P]
     lib.dom_agg_run.restype = I
+    lib.dom_agg_run_static.argtypes = [I, I, P, P, I64, P, P, I, I, P, P, U32, P]
+    lib.dom_agg_run_static.restype = I
     lib.dom_agg_plan_get_info.argtypes = [P, ctypes.POINTER(PlanInfo)]
     lib.dom_agg_plan_get_info.restype = I
     lib.dom_agg_plan_destroy.argtypes = [P]

@@ -78,16 +78,27 @@ dom_agg_status guarded(F &&f) {
 }
 
 // ---------------------------------------------------------------------------
-// Device memory: through the registered hook, else hipMalloc/hipFree.
+// Device memory: through the registered hook, else hipMalloc/hipFree; or,
+// inside dom_agg_run_static, from the static workspace (below).
 
 dom_agg_alloc_fn g_alloc = nullptr;
 dom_agg_release_fn g_release = nullptr;
 void *g_alloc_ctx = nullptr;
 
+// A bump allocator over one device's static workspace, active on the calling
+// thread for the duration of one dom_agg_run_static call.  Nothing is freed
+// during the call; the next call starts again at the beginning.
+struct Arena {
+    char *base;
+    size_t cap, used;
+};
+thread_local Arena *t_arena = nullptr;
+
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
     hipStream_t stream = nullptr;
+    bool from_arena = false;
 
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
@@ -99,24 +110,37 @@ struct DevBuf {
             p = o.p;
             bytes = o.bytes;
             stream = o.stream;
+            from_arena = o.from_arena;
             o.p = nullptr;
             o.bytes = 0;
+            o.from_arena = false;
         }
         return *this;
     }
     ~DevBuf() { reset(); }
     void reset() {
-        if (p) {
+        if (p && !from_arena) {
             if (g_release) g_release(p, stream, g_alloc_ctx);
             else (void)hipFree(p);
         }
         p = nullptr;
         bytes = 0;
+        from_arena = false;
     }
     void alloc(size_t b, hipStream_t s) {
         reset();
         if (b == 0) return;
         stream = s;
+        if (t_arena) {
+            const size_t at = (t_arena->used + 255) & ~(size_t)255;
+            if (at > t_arena->cap || b > t_arena->cap - at)
+                fail(DOM_AGG_ETOOBIG, "the call needs more than the %zu-byte static workspace", t_arena->cap);
+            p = t_arena->base + at;
+            bytes = b;
+            from_arena = true;
+            t_arena->used = at + b;
+            return;
+        }
         void *q = nullptr;
         if (g_alloc) {
             q = g_alloc(b, (void *)s, g_alloc_ctx);
@@ -250,6 +274,43 @@ constexpr uint64_t kMaxSlotBytes = 64ull << 30;
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// The static workspace of dom_agg_run_static.  Every GPU the library runs on
+// holds one copy of this array until the process ends.  Host code must not
+// use the array's name as a device address: the address of each device's
+// copy comes from hipGetSymbolAddress, taken once per device.
+
+constexpr size_t kStaticScratchBytes = 256ull << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+char *static_scratch(int dev) {
+    static std::mutex mu;
+    static std::map<int, char *> ptrs;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = ptrs.find(dev);
+    if (it != ptrs.end()) return it->second;
+    void *ptr = nullptr;  // (the calling thread has `dev` current)
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        fail(DOM_AGG_EHIP, "hipGetSymbolAddress of the static workspace: %s", hipGetErrorString(e));
+    }
+    ptrs.emplace(dev, static_cast<char *>(ptr));
+    return static_cast<char *>(ptr);
+}
+
+// Makes `a` the calling thread's allocator until the scope ends.
+struct ArenaScope {
+    explicit ArenaScope(Arena *a) { t_arena = a; }
+    ~ArenaScope() { t_arena = nullptr; }
+    ArenaScope(const ArenaScope &) = delete;
+    ArenaScope &operator=(const ArenaScope &) = delete;
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // The plan.
 
 struct dom_agg_plan_s {
@@ -338,6 +399,11 @@ namespace {
 using Plan = dom_agg_plan_s;
 
 // small pinned host staging for the plan's size reads
+// (inside dom_agg_run_static: a fixed host buffer, read after a stream
+// synchronisation, instead of pinned memory)
+constexpr size_t kStaticHostBytes = 1u << 20;
+thread_local unsigned char t_static_host[kStaticHostBytes];
+
 struct HostStage {
     void *p = nullptr;
     size_t bytes = 0;
@@ -345,6 +411,11 @@ struct HostStage {
         if (p) (void)hipHostFree(p);
     }
     void *get(size_t b) {
+        if (t_arena) {
+            if (b > kStaticHostBytes)
+                fail(DOM_AGG_ETOOBIG, "the call needs more than %zu bytes of host staging", kStaticHostBytes);
+            return t_static_host;
+        }
         if (b > bytes) {
             if (p) (void)hipHostFree(p);
             p = nullptr;
@@ -1506,6 +1577,36 @@ std::unique_ptr<Plan> make_plan(int m, dom_agg_dtype coord_dtype, const void *d_
     return P;
 }
 
+void check_run_args(int m, dom_agg_dtype coord_dtype, const void *d_coords, const void *q_coords,
+                    int64_t n_inst, const int64_t *d_offsets, const int64_t *q_offsets, dom_agg_op op,
+                    dom_agg_dtype weight_dtype, const void *weights, const void *out, uint32_t flags) {
+    check_plan_args(m, coord_dtype, d_coords, q_coords, n_inst, d_offsets, q_offsets);
+    if (flags & ~(uint32_t)(DOM_AGG_NO_TUNE | DOM_AGG_BASIC | le_flags(m)))
+        fail(DOM_AGG_EINVAL, "unknown flags 0x%x", flags);
+    check_basic(m, flags);
+    check_forward_args(op, weight_dtype, weights, out, d_offsets[n_inst], q_offsets[n_inst]);
+}
+
+// Plan + forward with records that carry the weights (dom_agg_run).
+void run_oneshot(int m, dom_agg_dtype coord_dtype, const void *d_coords, const void *q_coords, int64_t n_inst,
+                 const int64_t *d_offsets, const int64_t *q_offsets, dom_agg_op op, dom_agg_dtype weight_dtype,
+                 const void *weights, void *out, uint32_t flags, void *stream) {
+    check_run_args(m, coord_dtype, d_coords, q_coords, n_inst, d_offsets, q_offsets, op, weight_dtype, weights,
+                   out, flags);
+    if (q_offsets[n_inst] == 0) return;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // 4-byte weights (and no weights) travel inside the records
+    const bool inl = op == DOM_AGG_COUNT || weight_dtype == DOM_AGG_I32 || weight_dtype == DOM_AGG_F32;
+    auto P = make_plan(m, coord_dtype, d_coords, q_coords, n_inst, d_offsets, q_offsets, flags, s,
+                       op == DOM_AGG_COUNT ? nullptr : weights, weight_dtype, inl);
+    ensure_part(P.get(), value_bytes(op, weight_dtype), s);
+    const void *kp = P->rkeys.p;
+    const uint32_t *vp = P->rvals.as<uint32_t>();
+    if (P->key64) forward_dispatch<uint64_t>(P.get(), op, weight_dtype, kp, vp, weights, out, s);
+    else forward_dispatch<uint32_t>(P.get(), op, weight_dtype, kp, vp, weights, out, s);
+    // the plan's buffers go back stream-ordered (or through hipFree, which waits)
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1559,24 +1660,26 @@ dom_agg_status dom_agg_run(int m, dom_agg_dtype coord_dtype, const void *d_coord
                            dom_agg_dtype weight_dtype, const void *weights, void *out, uint32_t flags,
                            void *stream) {
     return guarded([&] {
-        check_plan_args(m, coord_dtype, d_coords, q_coords, n_inst, d_offsets, q_offsets);
-        if (flags & ~(uint32_t)(DOM_AGG_NO_TUNE | DOM_AGG_BASIC | le_flags(m)))
-            fail(DOM_AGG_EINVAL, "unknown flags 0x%x", flags);
-        check_basic(m, flags);
-        const int64_t nD = d_offsets[n_inst], nQ = q_offsets[n_inst];
-        check_forward_args(op, weight_dtype, weights, out, nD, nQ);
-        if (nQ == 0) return;
-        hipStream_t s = static_cast<hipStream_t>(stream);
-        // 4-byte weights (and no weights) travel inside the records
-        const bool inl = op == DOM_AGG_COUNT || weight_dtype == DOM_AGG_I32 || weight_dtype == DOM_AGG_F32;
-        auto P = make_plan(m, coord_dtype, d_coords, q_coords, n_inst, d_offsets, q_offsets, flags, s,
-                           op == DOM_AGG_COUNT ? nullptr : weights, weight_dtype, inl);
-        ensure_part(P.get(), value_bytes(op, weight_dtype), s);
-        const void *kp = P->rkeys.p;
-        const uint32_t *vp = P->rvals.as<uint32_t>();
-        if (P->key64) forward_dispatch<uint64_t>(P.get(), op, weight_dtype, kp, vp, weights, out, s);
-        else forward_dispatch<uint32_t>(P.get(), op, weight_dtype, kp, vp, weights, out, s);
-        // the plan's buffers go back stream-ordered (or through hipFree, which waits)
+        run_oneshot(m, coord_dtype, d_coords, q_coords, n_inst, d_offsets, q_offsets, op, weight_dtype, weights,
+                    out, flags, stream);
+    });
+}
+
+dom_agg_status dom_agg_run_static(int m, dom_agg_dtype coord_dtype, const void *d_coords, const void *q_coords,
+                                  int64_t n_inst, const int64_t *d_offsets, const int64_t *q_offsets,
+                                  dom_agg_op op, dom_agg_dtype weight_dtype, const void *weights, void *out,
+                                  uint32_t flags, void *stream) {
+    return guarded([&] {
+        check_run_args(m, coord_dtype, d_coords, q_coords, n_inst, d_offsets, q_offsets, op, weight_dtype,
+                       weights, out, flags);
+        if (q_offsets[n_inst] == 0) return;
+        int dev;
+        require_gfx950(&dev);
+        Arena arena{static_scratch(dev), kStaticScratchBytes, 0};
+        ArenaScope scope(&arena);
+        // (the tuner times candidates in buffers of their own: off here)
+        run_oneshot(m, coord_dtype, d_coords, q_coords, n_inst, d_offsets, q_offsets, op, weight_dtype, weights,
+                    out, flags | DOM_AGG_NO_TUNE, stream);
     });
 }
 

@@ -203,8 +203,10 @@ def _le_flags(le_mask: int) -> int:
 
 def dom_agg_run(d: torch.Tensor, q: torch.Tensor, w: torch.Tensor | None = None, op: str = "sum",
                 d_offsets=None, q_offsets=None, out: torch.Tensor | None = None, tune: bool = True,
-                le_mask: int = 0, basic: bool = False):
-    """One-shot forward (no plan is kept; the records carry the weights)."""
+                le_mask: int = 0, basic: bool = False, static: bool = False):
+    """One-shot forward (no plan is kept; the records carry the weights).
+    static: dom_agg_run_static, which allocates nothing (its workspace is a
+    static 256 MiB device array; out must be given or is allocated here)."""
     lib = _lib()
     d = _coords(d, "d")
     q = _coords(q, "q")
@@ -214,8 +216,9 @@ def dom_agg_run(d: torch.Tensor, q: torch.Tensor, w: torch.Tensor | None = None,
     doff, qoff = _offsets(nD, nQ, d_offsets, q_offsets)
     w, wdt = _weights(w, op, nD, d.device)
     out = _out(out, op, wdt, nQ, d.device)
+    fn = lib.dom_agg_run_static if static else lib.dom_agg_run
     with torch.cuda.device(d.device):
-        B.check(lib.dom_agg_run(int(d.shape[1]), _TORCH_TO_DT[d.dtype], _ptr(d), _ptr(q), int(doff.size - 1),
+        B.check(fn(int(d.shape[1]), _TORCH_TO_DT[d.dtype], _ptr(d), _ptr(q), int(doff.size - 1),
                                 doff.ctypes.data_as(ctypes.c_void_p), qoff.ctypes.data_as(ctypes.c_void_p),
                                 B.OPS[op], _TORCH_TO_DT.get(wdt, B.I64), _ptr(w) if op != "count" else None,
                                 _ptr(out), (0 if tune else B.NO_TUNE) | (B.BASIC if basic else 0) | _le_flags(le_mask),
