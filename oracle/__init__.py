@@ -20,6 +20,7 @@ from .oracle import (  # noqa: F401
     dense_rank,
     bits_for,
     fenwick2,
+    fenwick2_sums,
     sweep,
     final_list,
     identity,

@@ -14,6 +14,7 @@
  */
 #include <stdint.h>
 #include <stdlib.h>
+#include <string.h>
 #include <math.h>
 
 typedef struct {
@@ -119,5 +120,127 @@ int pin_fenwick2_i64(int64_t nD, const double *D, int64_t nQ, const double *Q,
         }
     }
     free(tree); free(p); free(u);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The same sweep for several weight columns at once (sums only), sorting
+ * with a radix sort instead of qsort, for pins at tens of millions of
+ * points.  W and out are column-major: W[c * nD + i], out[c * nQ + j].
+ * le_mask bit 0 / bit 1: <= instead of < on the first / second axis (the
+ * order of equal first coordinates, and the tree prefix that is asked for).
+ * is_int: W and out hold int64 instead of double. */
+
+static uint64_t sortable(double v) {
+    if (v == 0.0) v = 0.0; /* -0 and +0 are the same number */
+    uint64_t u;
+    memcpy(&u, &v, 8);
+    return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+
+/* stable LSD radix sort of (key, idx) by key, 8-bit digits; digits that are
+ * the same for every key are skipped.  Returns the sorted arrays (one of the
+ * two buffers of each kind). */
+static void radix_sort_u64(uint64_t **key, uint32_t **idx, uint64_t **key2, uint32_t **idx2, int64_t n) {
+    size_t cnt[256];
+    for (int pass = 0; pass < 8; pass++) {
+        const int sh = 8 * pass;
+        memset(cnt, 0, sizeof cnt);
+        for (int64_t i = 0; i < n; i++) cnt[((*key)[i] >> sh) & 255]++;
+        int trivial = 0;
+        for (int d = 0; d < 256; d++)
+            if (cnt[d] == (size_t)n) trivial = 1;
+        if (trivial) continue;
+        size_t sum = 0;
+        for (int d = 0; d < 256; d++) {
+            const size_t c = cnt[d];
+            cnt[d] = sum;
+            sum += c;
+        }
+        for (int64_t i = 0; i < n; i++) {
+            const size_t at = cnt[((*key)[i] >> sh) & 255]++;
+            (*key2)[at] = (*key)[i];
+            (*idx2)[at] = (*idx)[i];
+        }
+        uint64_t *tk = *key; *key = *key2; *key2 = tk;
+        uint32_t *ti = *idx; *idx = *idx2; *idx2 = ti;
+    }
+}
+
+int pin_fenwick2_multi(int64_t nD, const double *D, int64_t nQ, const double *Q, int nw, const void *W,
+                       int is_int, int le_mask, void *out) {
+    const int64_t n = nD + nQ;
+    if (nD < 0 || nQ < 0 || nw < 1 || n >= (int64_t)1 << 32) return -1;
+    for (int64_t i = 0; i < 2 * nD; i++)
+        if (isnan(D[i])) return -2;
+    for (int64_t j = 0; j < 2 * nQ; j++)
+        if (isnan(Q[j])) return -2;
+    const int le_x = le_mask & 1, le_y = (le_mask >> 1) & 1;
+    uint64_t *k1 = malloc(sizeof(uint64_t) * (size_t)(n + 1)), *k2 = malloc(sizeof(uint64_t) * (size_t)(n + 1));
+    uint32_t *i1 = malloc(sizeof(uint32_t) * (size_t)(n + 1)), *i2 = malloc(sizeof(uint32_t) * (size_t)(n + 1));
+    uint32_t *yr = malloc(sizeof(uint32_t) * (size_t)(n + 1));
+    if (!k1 || !k2 || !i1 || !i2 || !yr) {
+        free(k1); free(k2); free(i1); free(i2); free(yr);
+        return -3;
+    }
+    /* point p < nD is data row p, else query row p - nD */
+    /* dense ranks of the second coordinate */
+    for (int64_t p = 0; p < n; p++) {
+        k1[p] = sortable(p < nD ? D[2 * p + 1] : Q[2 * (p - nD) + 1]);
+        i1[p] = (uint32_t)p;
+    }
+    radix_sort_u64(&k1, &i1, &k2, &i2, n);
+    int64_t K = 0;
+    for (int64_t s = 0; s < n; s++) {
+        if (s == 0 || k1[s] != k1[s - 1]) K++;
+        yr[i1[s]] = (uint32_t)(K - 1);
+    }
+    /* sweep order: first coordinate ascending; on ties, queries first for <
+     * (the input order of a stable sort), data first for <= */
+    for (int64_t s = 0; s < n; s++) {
+        int64_t p;
+        if (le_x) p = s;                               /* data rows, then queries */
+        else p = s < nQ ? nD + s : s - nQ;             /* queries, then data rows */
+        k1[s] = sortable(p < nD ? D[2 * p] : Q[2 * (p - nD)]);
+        i1[s] = (uint32_t)p;
+    }
+    radix_sort_u64(&k1, &i1, &k2, &i2, n);
+    const size_t tsz = (size_t)(K + 1) * (size_t)nw;
+    double *tf = is_int ? NULL : calloc(tsz, sizeof(double));
+    int64_t *ti = is_int ? calloc(tsz, sizeof(int64_t)) : NULL;
+    if ((is_int && !ti) || (!is_int && !tf)) {
+        free(k1); free(k2); free(i1); free(i2); free(yr);
+        return -3;
+    }
+    const double *Wf = (const double *)W;
+    const int64_t *Wi = (const int64_t *)W;
+    double *of = (double *)out;
+    int64_t *oi = (int64_t *)out;
+    for (int64_t s = 0; s < n; s++) {
+        const int64_t p = i1[s];
+        const int64_t r = yr[p];
+        if (p >= nD) {
+            const int64_t j = p - nD;
+            /* ranks strictly below r (<), or up to r (<=) */
+            for (int c = 0; c < nw; c++) {
+                if (is_int) {
+                    int64_t acc = 0;
+                    for (int64_t i = r + le_y; i > 0; i -= i & (-i)) acc += ti[(size_t)i * nw + c];
+                    oi[(size_t)c * nQ + j] = acc;
+                } else {
+                    double acc = 0.0;
+                    for (int64_t i = r + le_y; i > 0; i -= i & (-i)) acc += tf[(size_t)i * nw + c];
+                    of[(size_t)c * nQ + j] = acc;
+                }
+            }
+        } else {
+            for (int64_t i = r + 1; i <= K; i += i & (-i))
+                for (int c = 0; c < nw; c++) {
+                    if (is_int) ti[(size_t)i * nw + c] += Wi[(size_t)c * nD + p];
+                    else tf[(size_t)i * nw + c] += Wf[(size_t)c * nD + p];
+                }
+        }
+    }
+    free(tf); free(ti); free(k1); free(k2); free(i1); free(i2); free(yr);
     return 0;
 }

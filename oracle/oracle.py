@@ -68,6 +68,7 @@ def _load():
     lib.pin_fenwick2_f64.argtypes = [I64, P, I64, P, P, I, D, P]
     lib.pin_fenwick2_i64.argtypes = [I64, P, I64, P, P, I, I64, P]
     lib.pin_cdq3_f64.argtypes = [I64, P, I64, P, P, I, D, I, P]
+    lib.pin_fenwick2_multi.argtypes = [I64, P, I64, P, I, P, I, I, P]
     lib.pin_cdq3_i64.argtypes = [I64, P, I64, P, P, I, I64, I, P]
     lib.oracle_brute_le_f64.argtypes = [I, I64, P, I64, P, P, I, D, I, P]
     lib.oracle_brute_le_i64.argtypes = [I, I64, P, I64, P, P, I, I64, I, P]
@@ -79,7 +80,7 @@ def _load():
                  "oracle_dom_agg_basic_i64", "oracle_transposed_sum_f64",
                  "oracle_sscan_f64", "oracle_prefix_set", "oracle_dense_rank",
                  "oracle_bits_for", "pin_fenwick2_f64", "pin_fenwick2_i64",
-                 "pin_cdq3_f64", "pin_cdq3_i64", "oracle_brute_le_f64", "oracle_brute_le_i64",
+                 "pin_cdq3_f64", "pin_cdq3_i64", "pin_fenwick2_multi", "oracle_brute_le_f64", "oracle_brute_le_i64",
                  "oracle_dom_agg_ex_f64", "oracle_dom_agg_ex_i64", "oracle_transposed_sum_le_f64"):
         getattr(lib, name).restype = I
     _lib = lib
@@ -306,3 +307,25 @@ def sweep(m, D, Q, w=None, op="sum", weight_dtype=None, le_mask=0):
         rc = lib.pin_cdq3_i64(nD, _ptr(D), nQ, _ptr(Q), _ptr(w), int(op_ == "max"), int(e), int(le_mask), _ptr(out))
     _check(rc, "sweep")
     return out
+
+
+def fenwick2_sums(D, Q, columns, le_mask=0):
+    """The m = 2 textbook sweep for several weight columns in one pass (sums
+    only; a pin at tens of millions of points).  columns: list of [|D|]
+    arrays, all float or all integer; returns one [|Q|] array per column
+    (float64 or int64)."""
+    lib = _load()
+    D = _coords(D, 2)
+    Q = _coords(Q, 2)
+    nD, nQ = D.shape[0], Q.shape[0]
+    is_int = all(np.asarray(c).dtype.kind in "iub" for c in columns)
+    vt = np.int64 if is_int else np.float64
+    W = np.ascontiguousarray(np.stack([np.asarray(c, dtype=vt) for c in columns]) if nD else
+                             np.zeros((len(columns), 0), dtype=vt))
+    if W.shape != (len(columns), nD):
+        raise OracleError("columns must have shape [nD]")
+    out = np.empty((len(columns), nQ), dtype=vt)
+    rc = lib.pin_fenwick2_multi(nD, _ptr(D), nQ, _ptr(Q), len(columns), _ptr(W), int(is_int), int(le_mask),
+                                _ptr(out))
+    _check(rc, "fenwick2_sums")
+    return [out[i] for i in range(len(columns))]

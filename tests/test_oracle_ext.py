@@ -240,3 +240,29 @@ def test_final_list_basic_variant():
     want = oracle.brute(2, c.D, c.Q, c.w, "sum")
     q = ids >= 60
     np.testing.assert_array_equal(vals[q], want[ids[q] - 60])
+
+
+# --------------------------------------------------------------------------
+# the multi-column Fenwick sweep (radix-sorted; the full-size pin for m = 2)
+
+
+@pytest.mark.parametrize("alpha,coord", [(5, "int"), (None, "f32"), (40, "f32")])
+def test_fenwick2_sums_equals_definition(alpha, coord):
+    c = _case(1600 + (alpha or 0), 2, 700, 650, alpha, weight="f64", coord=coord)
+    for le in range(4):
+        s, sa, n1 = oracle.fenwick2_sums(c.D, c.Q, [c.w, np.abs(c.w), np.ones_like(c.w)], le_mask=le)
+        np.testing.assert_allclose(s, oracle.brute(2, c.D, c.Q, c.w, "sum", le_mask=le), rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose(sa, oracle.brute(2, c.D, c.Q, np.abs(c.w), "sum", le_mask=le), rtol=1e-12)
+        np.testing.assert_array_equal(n1, oracle.brute(2, c.D, c.Q, None, "count", le_mask=le))
+        wi = (c.w * 100).astype(np.int64)
+        np.testing.assert_array_equal(oracle.fenwick2_sums(c.D, c.Q, [wi], le_mask=le)[0],
+                                      oracle.brute(2, c.D, c.Q, wi, "sum", le_mask=le))
+
+
+def test_fenwick2_sums_negative_zero_infinities_and_empty():
+    D = np.array([[-0.0, 1.0], [0.0, -np.inf], [np.inf, 0.0], [-1.0, -1.0]])
+    Q = np.array([[0.0, 2.0], [np.inf, np.inf], [1e-30, 0.5], [-0.0, 3.0]])
+    w = np.array([1.0, 2.0, 4.0, 8.0])
+    np.testing.assert_array_equal(oracle.fenwick2_sums(D, Q, [w])[0], oracle.brute(2, D, Q, w, "sum"))
+    assert oracle.fenwick2_sums(D[:0], Q, [w[:0]])[0].tolist() == [0.0] * 4
+    assert oracle.fenwick2_sums(D, Q[:0], [w])[0].size == 0
