@@ -190,7 +190,7 @@ def roofline_entry(kern, info, workload=None):
                            "divided by the number of passes"}
 
 
-def cpu_baseline(n_sample=1 << 19):
+def cpu_baseline(n_sample=1 << 20):
     import oracle
     import workloads
     c = workloads.f32_uniform(2, n_sample, workloads.BASE_SEED + 99, "sample")
@@ -251,7 +251,24 @@ def extra_fwd_bwd(steps):
             "backward_scan_ms": round(kern.get("backward_scan", (0, 1))[0] / steps, 4)}
 
 
+def _replay_ms(fn, reps):
+    """Average ms of fn() over reps calls (after one warm call), bracketed by
+    synchronisations."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps * 1e3
+
+
 def extra_batched(reps):
+    """4096 independent m = 2 instances (int coordinates, int64 weights, sum):
+    one batched plan + graph-replayed forward per step, against launching
+    plan + forward once per instance; plus the forward alone, replayed from
+    the kept plan's graph."""
     import torch
     import workloads
     from paper_2305_16751_amd import DomAggPlan
@@ -266,7 +283,11 @@ def extra_batched(reps):
         p.forward(w, "sum", out=out)
         p.close()
 
-    Tb, _ = time_steps(batched, reps, 1)
+    Tb, kern = time_steps(batched, reps, 1)
+    kept = DomAggPlan(d, q, c.d_offsets, c.q_offsets, graph=True)
+    info = kept.info()
+    fwd_ms = _replay_ms(lambda: kept.forward(w, "sum", out=out), 10)
+    kept.close()
     doff, qoff = c.d_offsets, c.q_offsets
 
     def per_instance():
@@ -277,10 +298,69 @@ def extra_batched(reps):
 
     Tp, _ = time_steps(per_instance, 1, 1)
     tb, tp = Tb / reps, Tp
-    return {"workload": "batched_int2d", "instances": len(doff) - 1, "points": c.n,
+    return {"workload": "batched_int2d", "instances": len(doff) - 1, "points": c.n, "records": info["records"],
             "batched_ms": round(tb * 1e3, 3), "per_instance_ms": round(tp * 1e3, 3),
             "batched_value": round(c.n / tb, 1), "per_instance_value": round(c.n / tp, 1),
-            "speedup": round(tp / tb, 2)}
+            "speedup": round(tp / tb, 2), "forward_replay_ms": round(fwd_ms, 3),
+            "stages": stage_table(kern, reps, info, c.n, 1, wbytes=8)}
+
+
+def extra_batched_gmm4d(reps):
+    """64 independent m = 4 instances (Gaussian-mixture points, fp32 weights):
+    batched plan + forward, plan + forward + backward (the fwd+bwd ratio),
+    the forward and backward alone replayed from the kept plan's graphs,
+    int32 max, and plan + forward launched once per instance."""
+    import torch
+    import workloads
+    from paper_2305_16751_amd import DomAggPlan
+    c = workloads.batched_gmm4d()
+    d = torch.from_numpy(c.D).cuda()
+    q = torch.from_numpy(c.Q).cuda()
+    w = torch.from_numpy(c.w).cuda()
+    wi = torch.from_numpy(c.w_alt).cuda()
+    g = torch.from_numpy(np.random.default_rng(5).standard_normal(c.Q.shape[0]).astype(np.float32)).cuda()
+    out = torch.empty(q.shape[0], device="cuda")
+    outi = torch.empty(q.shape[0], dtype=torch.int32, device="cuda")
+    gw = torch.empty(d.shape[0], device="cuda")
+    doff, qoff = c.d_offsets, c.q_offsets
+
+    def fwd():
+        p = DomAggPlan(d, q, doff, qoff, graph=True)
+        p.forward(w, "sum", out=out)
+        p.close()
+
+    def fwd_bwd():
+        p = DomAggPlan(d, q, doff, qoff, graph=True)
+        p.forward(w, "sum", out=out)
+        p.backward(g, out=gw)
+        p.close()
+
+    Tf, kern = time_steps(fwd, reps, 1)
+    Tb, _ = time_steps(fwd_bwd, reps, 1)
+    kept = DomAggPlan(d, q, doff, qoff, graph=True)
+    info = kept.info()
+    fwd_ms = _replay_ms(lambda: kept.forward(w, "sum", out=out), 5)
+    bwd_ms = _replay_ms(lambda: kept.backward(g, out=gw), 5)
+    max_ms = _replay_ms(lambda: kept.forward(wi, "max", out=outi), 5)
+    kept.close()
+
+    def per_instance():
+        for k in range(len(doff) - 1):
+            p = DomAggPlan(d[doff[k]:doff[k + 1]], q[qoff[k]:qoff[k + 1]])
+            p.forward(w[doff[k]:doff[k + 1]], "sum", out=out[qoff[k]:qoff[k + 1]])
+            p.close()
+
+    Tp, _ = time_steps(per_instance, 1, 1)
+    tf, tb, tp = Tf / reps, Tb / reps, Tp
+    return {"workload": "batched_gmm4d", "instances": len(doff) - 1, "points": c.n, "records": info["records"],
+            "key_bits": info["key_bits"], "regroup": "slots" if info["regroup_slots"] else "compact",
+            "plan_fwd_ms": round(tf * 1e3, 3), "value": round(c.n / tf, 1),
+            "plan_fwd_bwd_ms": round(tb * 1e3, 3), "fwd_bwd_ratio": round(tb / tf, 3),
+            "forward_replay_ms": round(fwd_ms, 3), "backward_replay_ms": round(bwd_ms, 3),
+            "max_int32_replay_ms": round(max_ms, 3),
+            "per_instance_ms": round(tp * 1e3, 3), "per_instance_value": round(c.n / tp, 1),
+            "speedup": round(tp / tf, 2),
+            "stages": stage_table(kern, reps, info, c.n, 3)}
 
 
 def main():
@@ -290,7 +370,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-extras", action="store_true", help="only the headline workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 19)
+    ap.add_argument("--cpu-sample", type=int, default=1 << 20)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB elementwise copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -341,7 +421,8 @@ def main():
         result["cpu_baseline"] = cpu_baseline(args.cpu_sample)
     if not args.no_extras:
         for name, fn in (("plan_forward", lambda: extra_plan_forward(case, 5)), ("m3", lambda: extra_m3(5)),
-                         ("fwd_bwd", lambda: extra_fwd_bwd(5)), ("batched", lambda: extra_batched(3))):
+                         ("fwd_bwd", lambda: extra_fwd_bwd(5)), ("batched", lambda: extra_batched(3)),
+                         ("batched_gmm4d", lambda: extra_batched_gmm4d(3))):
             log(f"extra: {name} ...")
             try:
                 extra[name] = fn()

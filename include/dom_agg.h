@@ -82,7 +82,8 @@ enum {
      * short.  Forward/backward then allocate, so they cannot be captured. */
     DOM_AGG_RECOMPUTE = 2,
     /* Capture forward/backward launches in a HIP graph on first use and
-     * replay it on later calls with the same arguments. */
+     * replay it on later calls with the same arguments (one graph is kept
+     * per distinct call: kind, op, dtypes and buffers; up to 8 per plan). */
     DOM_AGG_GRAPH = 4,
     /* Skip the autotuner and use the built-in tile and digit widths. */
     DOM_AGG_NO_TUNE = 8,
@@ -126,6 +127,8 @@ typedef struct {
     size_t workspace_bytes;/* device memory held by the plan */
     uint32_t le_mask;      /* bit a: <= on axis a (DOM_AGG_LE) */
     int32_t basic;         /* 1: the basic variant (DOM_AGG_BASIC), L has m entries */
+    int64_t graph_captures;/* DOM_AGG_GRAPH: graphs captured so far (a call whose
+                              arguments match a cached graph replays it) */
 } dom_agg_plan_info;
 
 /*
@@ -190,6 +193,28 @@ dom_agg_status dom_agg_plan(dom_agg_plan_t *plan, int m, dom_agg_dtype coord_dty
  */
 dom_agg_status dom_agg_forward(dom_agg_plan_t plan, dom_agg_op op, dom_agg_dtype weight_dtype,
                                const void *weights, void *out, void *stream);
+
+/*
+ * The forward with the final list of Sec. 4 (instructions 6m+6 .. 6m+9:
+ * sort by ID, shift, neutral_if_eq, segmented scan by ID) as its output:
+ * every expanded record once, in nondecreasing ID order, each carrying the
+ * total of its ID.  IDs follow the union of Sec. 4: data row i has ID i,
+ * query row j has ID n_data + j (rows of the whole batch).  A query's total
+ * is its result (dom_agg_forward); a data point's total is F over the
+ * partial aggregates the scan leaves at its own records (F over the data of
+ * each of its tuples up to it on the last axis), which the construction
+ * carries along.  Each ID appears once per record of its point (zero times
+ * when its prefix sets are empty).
+ *
+ *   op / weight_dtype / weights  as for dom_agg_forward.
+ *   ids    device, [E] int64 (E = dom_agg_plan_info.records), overwritten.
+ *   vals   device, [E] of the forward's output dtype, overwritten.
+ *
+ * Allocates its working buffers (not capturable).  Same numerics as the
+ * forward (integer and max exact; fp32 sums compensated).
+ */
+dom_agg_status dom_agg_forward_records(dom_agg_plan_t plan, dom_agg_op op, dom_agg_dtype weight_dtype,
+                                       const void *weights, int64_t *ids, void *vals, void *stream);
 
 /*
  * Backward of the SUM forward with respect to the weights: the transposed

@@ -34,6 +34,7 @@ EXPORTS = (
     "dom_agg_set_allocator",
     "dom_agg_plan",
     "dom_agg_forward",
+    "dom_agg_forward_records",
     "dom_agg_backward",
     "dom_agg_run",
     "dom_agg_run_static",
@@ -73,6 +74,7 @@ class PlanInfo(ctypes.Structure):
         ("workspace_bytes", ctypes.c_size_t),
         ("le_mask", ctypes.c_uint32),
         ("basic", ctypes.c_int32),
+        ("graph_captures", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:
@@ -110,6 +112,8 @@ def load(path: str | None = None):
     lib.dom_agg_plan.restype = I
     lib.dom_agg_forward.argtypes = [P, I, I, P, P, P]
     lib.dom_agg_forward.restype = I
+    lib.dom_agg_forward_records.argtypes = [P, I, I, P, P, P, P]
+    lib.dom_agg_forward_records.restype = I
     lib.dom_agg_backward.argtypes = [P, I, P, P, P]
     lib.dom_agg_backward.restype = I
     lib.dom_agg_run.argtypes = [I, I, P, P, I64, P, P, I, I, P, P, U32, P]

@@ -270,6 +270,7 @@ constexpr uint64_t kMaxRecords = (1ull << 32) - (1ull << 20);
 // enough; beyond these, the compact layout (one place per record)
 constexpr uint64_t kMaxSlots = 1024;
 constexpr uint64_t kMaxSlotBytes = 64ull << 30;
+constexpr size_t kMaxGraphs = 8;
 
 }  // namespace
 
@@ -373,9 +374,11 @@ struct dom_agg_plan_s {
     DevBuf ed_counter;
 
     // graph replay cache
+    // graph replay cache (DOM_AGG_GRAPH): one instantiated graph per call
+    // key (kind, op, dtypes, buffers), the oldest dropped beyond kMaxGraphs
     hipStream_t cap_stream = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    std::vector<uintptr_t> gkey;
+    std::vector<std::pair<std::vector<uintptr_t>, hipGraphExec_t>> graphs;
+    int64_t graph_captures = 0;
 
     size_t workspace() const {
         return off.bytes + rs.bytes + pay.bytes + inst_s.bytes + rank.bytes + inst_of_slot.bytes + ltab.bytes +
@@ -1279,6 +1282,115 @@ void forward_dispatch(Plan *P, dom_agg_op op, dom_agg_dtype wdt, const void *kp,
     }
 }
 
+// The final list of Sec. 4 (instructions 6m+6 .. 6m+9): the forward scan
+// keeping the partial aggregates of data records too, the regrouping of both
+// kinds by point (their totals), the records per ID and their offsets, the
+// IDs, and the broadcast of each ID's total along its run.
+template <class K, class W, class V, int OP>
+void records_run(Plan *P, const void *kp, const uint32_t *vp, const void *w, int64_t *ids, V *vals,
+                 hipStream_t s) {
+    const uint64_t nD = (uint64_t)P->nD, nQ = (uint64_t)P->nQ, n = (uint64_t)P->n, E = (uint64_t)P->E;
+    const int nax = P->nax;
+    DevBuf tq, td, totq, totd, wperm;
+    totq.alloc(std::max<uint64_t>(nQ, 1) * sizeof(V), s);
+    totd.alloc(std::max<uint64_t>(nD, 1) * sizeof(V), s);
+    if (nax > 0) {
+        const bool slots = P->use_slots;
+        tq.alloc(std::max<uint64_t>(slots ? (uint64_t)P->n_slots * nQ : E - P->E_D, 1) * sizeof(V), s);
+        td.alloc(std::max<uint64_t>(slots ? (uint64_t)P->n_slots * nD : P->E_D, 1) * sizeof(V), s);
+    }
+    ForwardProblem<K, W, V, OP, false> fp{};
+    fp.keys = static_cast<const K *>(kp);
+    fp.vals = vp;
+    fp.w = static_cast<const W *>(w);
+    fp.flag_shift = -1;
+    fp.nw = nD;
+    if constexpr (OP != OP_COUNT) {
+        if (P->permuted && nD > 0) {
+            wperm.alloc(nD * sizeof(W), s);
+            gather(static_cast<const W *>(w), P->dinv.as<uint32_t>(), wperm.as<W>(), nD, s);
+            fp.w = wperm.as<W>();
+        }
+    }
+    fp.sm = P->slot_map();
+    fp.q = part_dest<V>(P, true, nax == 0 ? totq.as<V>() : tq.as<V>());
+    fp.d = part_dest<V>(P, false, nax == 0 ? totd.as<V>() : td.as<V>());
+    using FP = ForwardProblem<K, W, V, OP, false>;
+    if (E > 0) {
+        if (P->tune.scan_items == 8 || sizeof(K) == 8)
+            scan_launch<FP, 8>("forward_scan", fp, E, P->scan_status.as<uint64_t>(), P->scan_words,
+                               P->scan_ticket.as<uint32_t>(), s);
+        else
+            scan_launch<FP, 16>("forward_scan", fp, E, P->scan_status.as<uint64_t>(), P->scan_words,
+                                P->scan_ticket.as<uint32_t>(), s);
+    }
+    if (nax > 0) {
+        regroup<V, OP>(P, true, tq.as<V>(), totq.as<V>(), s);
+        regroup<V, OP>(P, false, td.as<V>(), totd.as<V>(), s);
+    }
+    // records per ID, in ID order (data rows, then queries), and their offsets
+    DevBuf drow, qrow, off, status, ticket;
+    if (P->permuted) {
+        drow.alloc(std::max<uint64_t>(nD, 1) * 4, s);
+        qrow.alloc(std::max<uint64_t>(nQ, 1) * 4, s);
+        launch("invert_perm", s, [&] {
+            invert_perm_kernel<<<grid_for(nD), kBlock, 0, s>>>(P->dinv.as<uint32_t>(), nD, drow.as<uint32_t>());
+        });
+        launch("invert_perm", s, [&] {
+            invert_perm_kernel<<<grid_for(nQ), kBlock, 0, s>>>(P->qinv.as<uint32_t>(), nQ, qrow.as<uint32_t>());
+        });
+    }
+    off.alloc((n + 1) * 8, s);
+    IdCountProblem ip{};
+    ip.drow_pos = drow.as<uint32_t>();
+    ip.qrow_pos = qrow.as<uint32_t>();
+    ip.rank = P->rank.as<uint32_t>();
+    ip.inst_of_slot = P->inst_of_slot.as<uint32_t>();
+    ip.ltab = P->ltab.as<uint8_t>();
+    ip.n = (uint32_t)n;
+    ip.nD = (uint32_t)nD;
+    ip.nQ = (uint32_t)nQ;
+    ip.n_inst = (uint32_t)P->n_inst;
+    ip.nax = nax;
+    ip.off = off.as<uint64_t>();
+    const uint64_t words = 2 * ceil_div(std::max(n, E), (uint64_t)kBlock * 8) * 2;
+    status.alloc(words * 8, s);
+    ticket.alloc(16, s);
+    scan_launch<IdCountProblem, 8>("id_offsets", ip, n, status.as<uint64_t>(), words, ticket.as<uint32_t>(), s);
+    launch("id_fill", s, [&] { id_fill_kernel<<<grid_for(n), kBlock, 0, s>>>(off.as<uint64_t>(), (uint32_t)n, E, ids); });
+    BroadcastProblem<V, OP> bp{};
+    bp.ids = ids;
+    bp.tot_d = totd.as<V>();
+    bp.tot_q = totq.as<V>();
+    bp.nD = nD;
+    bp.nQ = nQ;
+    bp.vals = vals;
+    scan_launch<BroadcastProblem<V, OP>, 8>("broadcast", bp, E, status.as<uint64_t>(), words, ticket.as<uint32_t>(),
+                                            s);
+}
+
+template <class K>
+void records_dispatch(Plan *P, dom_agg_op op, dom_agg_dtype wdt, const void *kp, const uint32_t *vp, const void *w,
+                      int64_t *ids, void *vals, hipStream_t s) {
+    if (op == DOM_AGG_COUNT)
+        return records_run<K, uint8_t, int64_t, OP_COUNT>(P, kp, vp, w, ids, static_cast<int64_t *>(vals), s);
+    if (op == DOM_AGG_SUM) {
+        switch (wdt) {
+            case DOM_AGG_I32: return records_run<K, int32_t, int64_t, OP_SUM>(P, kp, vp, w, ids, static_cast<int64_t *>(vals), s);
+            case DOM_AGG_I64: return records_run<K, int64_t, int64_t, OP_SUM>(P, kp, vp, w, ids, static_cast<int64_t *>(vals), s);
+            case DOM_AGG_F32: return records_run<K, float, float, OP_SUM>(P, kp, vp, w, ids, static_cast<float *>(vals), s);
+            case DOM_AGG_F64: return records_run<K, double, double, OP_SUM>(P, kp, vp, w, ids, static_cast<double *>(vals), s);
+        }
+    } else {
+        switch (wdt) {
+            case DOM_AGG_I32: return records_run<K, int32_t, int32_t, OP_MAX>(P, kp, vp, w, ids, static_cast<int32_t *>(vals), s);
+            case DOM_AGG_I64: return records_run<K, int64_t, int64_t, OP_MAX>(P, kp, vp, w, ids, static_cast<int64_t *>(vals), s);
+            case DOM_AGG_F32: return records_run<K, float, float, OP_MAX>(P, kp, vp, w, ids, static_cast<float *>(vals), s);
+            case DOM_AGG_F64: return records_run<K, double, double, OP_MAX>(P, kp, vp, w, ids, static_cast<double *>(vals), s);
+        }
+    }
+}
+
 template <class K, class G>
 void backward_typed(Plan *P, const void *kp, const uint32_t *vp, const void *g, void *grad, hipStream_t s) {
     BackwardProblem<K, G> bp{};
@@ -1310,10 +1422,13 @@ void maybe_graph(Plan *P, const std::vector<uintptr_t> &key, hipStream_t s, F &&
         body(s);
         return;
     }
-    if (!P->gexec || P->gkey != key) {
-        if (P->gexec) {
-            (void)hipGraphExecDestroy(P->gexec);
-            P->gexec = nullptr;
+    hipGraphExec_t exec = nullptr;
+    for (auto &g : P->graphs)
+        if (g.first == key) exec = g.second;
+    if (!exec) {
+        if (P->graphs.size() >= kMaxGraphs) {
+            (void)hipGraphExecDestroy(P->graphs.front().second);
+            P->graphs.erase(P->graphs.begin());
         }
         if (!P->cap_stream) HIPCHK(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
         hipGraph_t g = nullptr;
@@ -1330,14 +1445,13 @@ void maybe_graph(Plan *P, const std::vector<uintptr_t> &key, hipStream_t s, F &&
         }
         t_capturing = false;
         HIPCHK(hipStreamEndCapture(P->cap_stream, &g));
-        hipGraphExec_t ex = nullptr;
-        const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        const hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         HIPCHK(e);
-        P->gexec = ex;
-        P->gkey = key;
+        P->graphs.emplace_back(key, exec);
+        P->graph_captures++;
     }
-    launch("graph_replay", s, [&] { HIPCHK(hipGraphLaunch(P->gexec, s)); });
+    launch("graph_replay", s, [&] { HIPCHK(hipGraphLaunch(exec, s)); });
 }
 
 
@@ -1707,6 +1821,26 @@ dom_agg_status dom_agg_forward(dom_agg_plan_t plan, dom_agg_op op, dom_agg_dtype
     });
 }
 
+dom_agg_status dom_agg_forward_records(dom_agg_plan_t plan, dom_agg_op op, dom_agg_dtype weight_dtype,
+                                       const void *weights, int64_t *ids, void *vals, void *stream) {
+    return guarded([&] {
+        if (!plan) fail(DOM_AGG_EINVAL, "plan is NULL");
+        check_forward_args(op, weight_dtype, weights, vals, plan->nD, plan->E);
+        if (plan->E > 0 && !ids) fail(DOM_AGG_EINVAL, "ids is NULL");
+        if (plan->E == 0) return;
+        int dev;
+        require_gfx950(&dev);
+        if (dev != plan->device) fail(DOM_AGG_EINVAL, "plan belongs to device %d, current is %d", plan->device, dev);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        DevBuf k, v;
+        const void *kp = nullptr;
+        const uint32_t *vp = nullptr;
+        records_for_call(plan, s, k, v, &kp, &vp);
+        if (plan->key64) records_dispatch<uint64_t>(plan, op, weight_dtype, kp, vp, weights, ids, vals, s);
+        else records_dispatch<uint32_t>(plan, op, weight_dtype, kp, vp, weights, ids, vals, s);
+    });
+}
+
 dom_agg_status dom_agg_backward(dom_agg_plan_t plan, dom_agg_dtype grad_dtype, const void *grad_out,
                                 void *grad_weights, void *stream) {
     return guarded([&] {
@@ -1764,13 +1898,14 @@ dom_agg_status dom_agg_plan_get_info(dom_agg_plan_t plan, dom_agg_plan_info *inf
             info->sort_class_records[0] = plan->E;
         info->workspace_bytes = plan->workspace();
         info->le_mask = plan->le_mask;
+        info->graph_captures = plan->graph_captures;
         info->basic = plan->basic ? 1 : 0;
     });
 }
 
 void dom_agg_plan_destroy(dom_agg_plan_t plan) {
     if (!plan) return;
-    if (plan->gexec) (void)hipGraphExecDestroy(plan->gexec);
+    for (auto &g : plan->graphs) (void)hipGraphExecDestroy(g.second);
     if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
     delete plan;
 }

@@ -1671,3 +1671,109 @@ struct CompactStateProblem {
 };
 
 }  // namespace domagg
+
+namespace domagg {
+
+// ---------------------------------------------------------------------------
+// The final list of Sec. 4 (instructions 6m+6 .. 6m+9): every record once,
+// in nondecreasing ID order (data row i has ID i, query row j has ID
+// |D| + j), each carrying the total of its ID -- the query's result, or for
+// a data point F over the partial aggregates at its own records.
+
+// inv[perm[i]] = i (perm a permutation of [0, n); other indices dropped).
+__global__ void invert_perm_kernel(const uint32_t *__restrict__ perm, uint64_t n, uint32_t *__restrict__ inv) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint32_t p = perm[i];
+        if (p < n) inv[p] = (uint32_t)i;
+    }
+}
+
+// Records per ID (the size of the point's product of prefix sets) and their
+// exclusive sums: off[id] = the list position of ID id's first entry,
+// off[n] = E.
+struct IdCountProblem {
+    using V = uint64_t;
+    using Raw = uint32_t;
+    const uint32_t *drow_pos;      // [nD] internal position of each data row, or null (identity)
+    const uint32_t *qrow_pos;      // [nQ] likewise for queries
+    const uint32_t *rank;          // [nax][n] by internal slot
+    const uint32_t *inst_of_slot;  // [n] or null
+    const uint8_t *ltab;           // [nax][n_inst]
+    uint32_t n, nD, nQ, n_inst;
+    int nax;
+    uint64_t *off;                 // [n + 1]
+
+    __device__ V identity() const { return 0ull; }
+    __device__ V combine(V a, V b) const { return a + b; }
+    __device__ Raw load(uint64_t i) const { return (uint32_t)i; }
+    __device__ bool head(const Raw &, const Raw &) const { return false; }
+    __device__ V value(const Raw &, bool, const Raw &id, uint64_t) const {
+        const bool isq = id >= nD;
+        uint32_t slot;
+        if (isq) {
+            const uint32_t j = id - nD;
+            slot = qrow_pos ? qrow_pos[j] : j;
+        } else {
+            slot = nQ + (drow_pos ? drow_pos[id] : id);
+        }
+        if (slot >= n) return 0ull;  // (positions are below |D| and |Q| by construction)
+        const uint32_t ins = inst_of_slot ? inst_of_slot[slot] : 0u;
+        uint64_t c = 1;
+        for (int a = 0; a < nax; ++a) {
+            const uint32_t r = rank[(uint64_t)a * n + slot];
+            const uint32_t L = ltab[(uint64_t)a * n_inst + (ins < n_inst ? ins : 0u)];
+            const uint32_t pc = (uint32_t)__popc(r);
+            c *= isq ? pc : (L > pc ? L - pc : 0u);
+        }
+        return c;
+    }
+    __device__ void emit(uint64_t i, const Raw &, V, V excl, V incl, bool) const {
+        off[i] = excl;
+        if (i == (uint64_t)n - 1) off[n] = incl;
+    }
+};
+
+// ids[off[id] .. off[id + 1]) = id.
+__global__ void id_fill_kernel(const uint64_t *__restrict__ off, uint32_t n, uint64_t cap,
+                               int64_t *__restrict__ ids) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t id = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; id < n; id += stride) {
+        uint64_t hi = off[id + 1];
+        if (hi > cap) hi = cap;  // (off[n] = E = cap by construction)
+        for (uint64_t i = off[id]; i < hi; ++i) ids[i] = (int64_t)id;
+    }
+}
+
+// Instructions 6m+7 .. 6m+9 over the list sorted by ID: H = the IDs shifted
+// right by one; the value is e wherever the ID equals H (neutral_if_eq),
+// else the ID's total (its first entry, where the complete aggregate sits
+// after the reversal of 6m+6); the segmented scan tagged by ID then carries
+// it to every entry of the run.
+template <class Out, int OP>
+struct BroadcastProblem {
+    using V = typename AccumOf<Out, OP>::type;
+    struct Raw {
+        int64_t id;
+    };
+    const int64_t *ids;  // [E]
+    const Out *tot_d;    // [nD] totals of the data rows
+    const Out *tot_q;    // [nQ] totals of the queries
+    uint64_t nD, nQ;
+    Out *vals;           // [E]
+
+    __device__ V identity() const { return Monoid<V, OP>::identity(); }
+    __device__ V combine(V a, V b) const { return Monoid<V, OP>::combine(a, b); }
+    __device__ Raw load(uint64_t i) const { return Raw{ids[i]}; }
+    __device__ bool head(const Raw &prev, const Raw &cur) const { return prev.id != cur.id; }
+    __device__ V value(const Raw &prev, bool has_prev, const Raw &cur, uint64_t) const {
+        if (has_prev && prev.id == cur.id) return identity();  // neutral_if_eq
+        const uint64_t id = (uint64_t)cur.id;
+        if (id < nD) return acc_from<V>(tot_d[id]);
+        if (id - nD < nQ) return acc_from<V>(tot_q[id - nD]);
+        return identity();  // (IDs are below |D| + |Q| by construction)
+    }
+    __device__ void emit(uint64_t i, const Raw &, V, V, V incl, bool) const { vals[i] = acc_out<Out>(incl); }
+};
+
+}  // namespace domagg

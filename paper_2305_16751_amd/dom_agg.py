@@ -161,6 +161,20 @@ class DomAggPlan:
                                               _ptr(w) if op != "count" else None, _ptr(out), _stream()))
         return out
 
+    def forward_records(self, w: torch.Tensor | None = None, op: str = "sum"):
+        """The final list of Sec. 4: (ids [E] int64, vals [E]), every record in
+        nondecreasing ID order (data rows 0..|D|-1, then queries |D|..), each
+        with the total of its ID."""
+        w, wdt = _weights(w, op, self.nD, self.device)
+        E = self.info()["records"]
+        ids = torch.empty(E, dtype=torch.int64, device=self.device)
+        vals = torch.empty(E, dtype=_out_dtype(op, wdt), device=self.device)
+        with torch.cuda.device(self.device):
+            B.check(self._lib.dom_agg_forward_records(self._h, B.OPS[op], _TORCH_TO_DT.get(wdt, B.I64),
+                                                      _ptr(w) if op != "count" else None, _ptr(ids), _ptr(vals),
+                                                      _stream()))
+        return ids, vals
+
     def backward(self, grad_out: torch.Tensor, out: torch.Tensor | None = None):
         if grad_out.dtype not in (torch.float32, torch.float64) or grad_out.shape != (self.nQ,):
             raise ValueError(f"grad_out must be a [{self.nQ}] float32 or float64 tensor")

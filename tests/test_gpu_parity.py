@@ -205,6 +205,30 @@ def test_graph_replay_matches_eager():
         torch.cuda.synchronize()
 
 
+def test_graph_cache_alternating_forward_backward():
+    """A training loop alternating forward and backward on one graph plan
+    replays one graph per call kind instead of capturing again; every
+    replay equals the eager result."""
+    c = workloads.small_case(14, 2, 20000, 20000, alphabet=None, coord="f32", weight="f32")
+    eager = _plan(c)
+    w = to_dev(c.w)
+    g = to_dev(np.random.default_rng(2).standard_normal(c.Q.shape[0]).astype(np.float32))
+    fe, be = eager.forward(w, "sum").cpu().numpy(), eager.backward(g).cpu().numpy()
+    p = _plan(c, graph=True)
+    out = torch.empty(c.Q.shape[0], device=DEV)
+    gw = torch.empty(c.D.shape[0], device=DEV)
+    for r in range(4):
+        p.forward(w, "sum", out=out)
+        p.backward(g, out=gw)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), fe), f"forward replay {r}"
+        assert np.array_equal(gw.cpu().numpy(), be), f"backward replay {r}"
+        out.fill_(3.0)  # eager work between replays
+        gw.fill_(-3.0)
+        torch.cuda.synchronize()
+    assert p.info()["graph_captures"] == 2, p.info()
+
+
 def test_autograd_function():
     from paper_2305_16751_amd import dom_agg
     c = workloads.small_case(11, 2, 3000, 2500, alphabet=None, coord="f32", weight="f32")
