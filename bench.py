@@ -36,18 +36,21 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def key_bytes(info, kernel=None):
-    """Bytes of a record key: from the record-sort kernel's name when given
-    (records that carry weights may use 64-bit keys for the query flag)."""
+def record_bytes(info, kernel=None):
+    """Bytes of one sorted record: from the record-sort kernel's name when
+    given (8 for records packed into one word, else key + 4-byte payload),
+    else from the plan."""
     if kernel is not None:
-        return 8 if "_u64_" in kernel else 4
-    return 4 if info["key_bits"] <= 32 else 8
+        if "packed" in kernel:
+            return 8
+        return 12 if "_u64_" in kernel else 8
+    return info["record_bytes"]
 
 
 def record_sort_model(info, kernel=None):
     """Algorithmic bytes of the record sort and its number of digit passes:
     each pass reads and writes every record of its key-length class once."""
-    rb = key_bytes(info, kernel) + 4
+    rb = record_bytes(info, kernel)
     ncls = info["sort_classes"]
     total, launches = 0, 0
     for c, ec in enumerate(info["sort_class_records"]):
@@ -65,11 +68,11 @@ def stage_table(kern, steps, info, n, nax, wbytes=4):
     ED = info["data_records"]
     EQ = E - ED
     rec = [k for k in kern if k.startswith("onesweep_records")]
-    kb = key_bytes(info, rec[0] if rec else None)
+    rb = record_bytes(info, rec[0] if rec else None)
     model = {
-        "flatmap_emit": E * (kb + 4) + n * (8 + 4 + 4 * nax),
-        "forward_scan": E * (kb + 4) + ED * wbytes + EQ * wbytes,
-        "backward_scan": E * (kb + 4) + EQ * wbytes + ED * wbytes,
+        "flatmap_emit": E * rb + n * (8 + 4 + 4 * nax),
+        "forward_scan": E * rb + ED * wbytes + EQ * wbytes,
+        "backward_scan": E * rb + EQ * wbytes + ED * wbytes,
     }
     out = {}
     for name, (ms, cnt) in sorted(kern.items(), key=lambda kv: -kv[1][0]):
@@ -185,9 +188,9 @@ def roofline_entry(kern, info, workload=None):
             "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": measured_traffic(name, workload) if workload else None,
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "bytes_per_launch": round(b), "avg_launch_ms": round(avg_s * 1e3, 5),
-            "bytes_model": "sum over key-length classes of passes_c * 2 * E_c * (key bytes + 4 payload bytes) "
-                           "(every record of a class read and written once per pass of its class), "
-                           "divided by the number of passes"}
+            "bytes_model": "sum over key-length classes of passes_c * 2 * E_c * record bytes (8 when key and "
+                           "payload are packed into one word, else key bytes + 4) (every record of a class "
+                           "read and written once per pass of its class), divided by the number of passes"}
 
 
 def cpu_baseline(n_sample=1 << 20):

@@ -129,6 +129,8 @@ typedef struct {
     int32_t basic;         /* 1: the basic variant (DOM_AGG_BASIC), L has m entries */
     int64_t graph_captures;/* DOM_AGG_GRAPH: graphs captured so far (a call whose
                               arguments match a cached graph replays it) */
+    int32_t record_bytes;  /* bytes per sorted record: 8 when key and payload are
+                              packed into one 64-bit word, else key + 4 */
 } dom_agg_plan_info;
 
 /*

@@ -75,6 +75,7 @@ class PlanInfo(ctypes.Structure):
         ("le_mask", ctypes.c_uint32),
         ("basic", ctypes.c_int32),
         ("graph_captures", ctypes.c_int64),
+        ("record_bytes", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:

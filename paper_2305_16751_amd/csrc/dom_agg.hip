@@ -256,6 +256,16 @@ void require_gfx950(int *device) {
     *device = dev;
 }
 
+// DOM_AGG_PACK=0 keeps records as separate key and payload arrays (for
+// measurement); packing is on otherwise.
+bool packing_enabled() {
+    static const bool on = [] {
+        const char *e = std::getenv("DOM_AGG_PACK");
+        return !(e && e[0] == '0');
+    }();
+    return on;
+}
+
 int bits_for(uint64_t K) {
     int L = 0;
     while (L < 63 && (1ull << L) < K) ++L;
@@ -354,6 +364,9 @@ struct dom_agg_plan_s {
     // digit histograms are counted from them per tree node)
     DevBuf cdf_d, cdf_q;
     uint32_t K0 = 0;
+    // records as packed 64-bit words (key above pay_bits payload bits)
+    bool packed = false;
+    int pay_bits = 0;
     // records carrying weights (one-shot calls): requested, granted, the
     // query flag's bit in the record key, the weights and their dtype
     bool inline_req = false, inline_w = false;
@@ -551,6 +564,50 @@ bool radix_sort(K *kA, VT *vA, K *kB, VT *vB, uint64_t n, const std::vector<int>
         ++pass;
     }
     // status/ticket are released stream-ordered (or by hipFree, which waits)
+    return inB;
+}
+
+// Sorts packed 64-bit records (key above pay_bits payload bits) by the
+// listed key digit shifts; returns true when the result ended up in B.
+bool radix_sort_packed(uint64_t *A, uint64_t *B, uint64_t n, const std::vector<int> &shifts, int pay_bits,
+                       const uint32_t *bases, int tile, hipStream_t s) {
+    if (n == 0 || shifts.empty()) return false;
+    tile = tile == 4096 ? 4096 : 8192;
+    const bool narrow = n < (1ull << 30);
+    const uint64_t pass_words = ceil_div(ceil_div(n, (uint64_t)tile) * kRadix * (narrow ? 4 : 8), (uint64_t)8);
+    const uint64_t np = shifts.size();
+    DevBuf status;
+    status.alloc((pass_words * np + ceil_div(np, (uint64_t)2) + 1) * 8, s);
+    uint32_t *tickets = reinterpret_cast<uint32_t *>(status.as<uint64_t>() + pass_words * np);
+    clear_lookback(status.as<uint64_t>(), pass_words * np + ceil_div(np, (uint64_t)2) + 1, tickets, s);
+    bool inB = false;
+    uint64_t pass = 0;
+    for (int sh : shifts) {
+        const uint64_t *in = inB ? B : A;
+        uint64_t *out = inB ? A : B;
+        const uint32_t *b = bases + (sh / kRadixBits) * kRadix;
+        void *st = status.as<uint64_t>() + pass * pass_words;
+        const unsigned tiles = (unsigned)ceil_div(n, (uint64_t)tile);
+        const int shift = pay_bits + sh;
+        auto go = [&](auto s_c) {
+            using S = decltype(s_c);
+            S *stw = static_cast<S *>(st);
+            if (tile == 4096)
+                launch("onesweep_records_packed_t4096", s, [&] {
+                    onesweep_kernel<uint64_t, S, 256, 16, 1, uint32_t, false><<<tiles, 256, 0, s>>>(
+                        in, nullptr, out, nullptr, (uint32_t)n, shift, b, stw, tickets + pass);
+                });
+            else
+                launch("onesweep_records_packed_t8192", s, [&] {
+                    onesweep_kernel<uint64_t, S, 512, 16, 1, uint32_t, false><<<tiles, 512, 0, s>>>(
+                        in, nullptr, out, nullptr, (uint32_t)n, shift, b, stw, tickets + pass);
+                });
+        };
+        if (narrow) go(uint32_t{});
+        else go(uint64_t{});
+        inB = !inB;
+        ++pass;
+    }
     return inB;
 }
 
@@ -756,15 +813,26 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
     P->key_bits = sum + (P->batched ? P->inst_bits : 0);
     if (P->key_bits > 64) fail(DOM_AGG_ETOOBIG, "record sort key needs %d bits (> 64)", P->key_bits);
     P->key64 = P->key_bits > 32;
+    // Records as single 64-bit words when key and payload fit: 32 weight
+    // bits with the query flag above the key's digits (records carrying
+    // weights), else a flagged label of 1 + ceil(log2 max(|D|, |Q|)) bits.
+    // Records carry their weights only when that packs (or packing is off):
+    // a label record packs into fewer bytes than an unpacked weight record.
+    const bool pack_ok = packing_enabled();
+    P->pay_bits = 1 + bits_for((uint64_t)std::max<int64_t>(std::max(P->nD, P->nQ), 1));
     if (P->inline_req && nax > 0) {
         // the query flag goes one bit above the digits the record sort reads
         const int fs = kRadixBits * std::max(1, (int)ceil_div(P->key_bits, kRadixBits));
-        if (fs < 64) {
+        const bool packs = pack_ok && fs + 1 + 32 <= 64;
+        if (fs < 64 && (packs || !pack_ok)) {
             P->inline_w = true;
             P->flag_shift = fs;
             P->key64 = fs >= 32;
+            P->packed = packs;
+            if (packs) P->pay_bits = 32;
         }
     }
+    if (!P->inline_w && pack_ok && P->key_bits + P->pay_bits <= 64) P->packed = true;
     DevBuf sig_vals64;
     if (sigv) {
         DevBuf wA, wB;
@@ -915,11 +983,18 @@ void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &ou
     const uint64_t E = (uint64_t)P->E;
     const bool cls = P->ncls > 1;
     DevBuf kA, kB, vA, vB, part, counts, bases, cstat, ticket;
-    kA.alloc(E * sizeof(K), s);
-    vA.alloc(E * 4, s);
-    if (cls) {
-        kB.alloc(E * sizeof(K), s);
-        vB.alloc(E * 4, s);
+    const bool pk = P->packed;
+    if (pk) {
+        // packed words live in the key buffers; no payload arrays
+        kA.alloc(E * 8, s);
+        if (cls) kB.alloc(E * 8, s);
+    } else {
+        kA.alloc(E * sizeof(K), s);
+        vA.alloc(E * 4, s);
+        if (cls) {
+            kB.alloc(E * sizeof(K), s);
+            vB.alloc(E * 4, s);
+        }
     }
     const int passes = cls ? P->cls_passes[P->ncls - 1] : std::max(1, (int)ceil_div(P->key_bits, kRadixBits));
     const int rows = cls ? P->cls_rows : passes;
@@ -981,6 +1056,10 @@ void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &ou
     a.data_records = P->ed_counter.as<unsigned long long>();
     a.wv = P->inline_w ? P->wv.as<uint32_t>() : nullptr;
     a.flag_shift = P->inline_w ? P->flag_shift : -1;
+    a.pk_a = pk ? kA.as<uint64_t>() : nullptr;
+    a.pk_b = pk && cls ? kB.as<uint64_t>() : nullptr;
+    a.pk_shift = P->pay_bits;
+    a.pk_labels = !P->inline_w;
     a.ncls = P->ncls;
     a.cls_c0 = P->cls_c0;
     a.hist_rows = rows;
@@ -1052,18 +1131,18 @@ void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &ou
     fill(ticket.as<uint32_t>(), 2, 0u, s);  // (word 1: the error flag)
     a.cls_off = cstat.as<uint32_t>();
     a.error = ticket.as<uint32_t>() + 1;
+    // (packed records: the key and payload arrays are not written)
+    K *ka = pk ? nullptr : kA.as<K>(), *kb = pk ? nullptr : kB.as<K>();
+    uint32_t *va = vA.as<uint32_t>(), *vb = vB.as<uint32_t>();
     per_nax([&](auto nax_c) {
         constexpr int NAX = decltype(nax_c)::value;
         launch("flatmap_emit", s, [&] {
             if (cls && !a.hist_part)
-                emit_kernel<K, NAX, kBlock, EITEMS, true, false><<<grid, kBlock, 0, s>>>(
-                    a, kA.as<K>(), vA.as<uint32_t>(), kB.as<K>(), vB.as<uint32_t>());
+                emit_kernel<K, NAX, kBlock, EITEMS, true, false><<<grid, kBlock, 0, s>>>(a, ka, va, kb, vb);
             else if (cls)
-                emit_kernel<K, NAX, kBlock, EITEMS, true><<<grid, kBlock, 0, s>>>(a, kA.as<K>(), vA.as<uint32_t>(),
-                                                                                  kB.as<K>(), vB.as<uint32_t>());
+                emit_kernel<K, NAX, kBlock, EITEMS, true><<<grid, kBlock, 0, s>>>(a, ka, va, kb, vb);
             else
-                emit_kernel<K, NAX, kBlock, EITEMS, false><<<grid, kBlock, 0, s>>>(a, kA.as<K>(), vA.as<uint32_t>(),
-                                                                                   nullptr, nullptr);
+                emit_kernel<K, NAX, kBlock, EITEMS, false><<<grid, kBlock, 0, s>>>(a, ka, va, nullptr, nullptr);
         });
     });
     if (node_hist) reduce_hist(npart.as<uint32_t>(), (int)ngrid, rows, counts.as<uint32_t>(), bases.as<uint32_t>(), s);
@@ -1096,7 +1175,11 @@ void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &ou
             for (int p = 0; p < np; ++p) shifts.push_back(p * kRadixBits);
             const uint64_t b = a.cls_base[q];
             const uint32_t *cb = bases.as<uint32_t>() + (size_t)P->cls_row0[q] * kRadix;
-            if (np & 1)
+            if (pk) {
+                uint64_t *pa = kA.as<uint64_t>() + b, *pb = kB.as<uint64_t>() + b;
+                if (np & 1) radix_sort_packed(pa, pb, nq, shifts, P->pay_bits, cb, P->tune.record_sort_tile, s);
+                else radix_sort_packed(pb, pa, nq, shifts, P->pay_bits, cb, P->tune.record_sort_tile, s);
+            } else if (np & 1)
                 radix_sort<K, 1>(kA.as<K>() + b, vA.as<uint32_t>() + b, kB.as<K>() + b, vB.as<uint32_t>() + b, nq,
                                  shifts, cb, P->tune.record_sort_tile, s);
             else
@@ -1109,13 +1192,34 @@ void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &ou
     }
     bool inB = false;
     if (!P->rec_shifts.empty()) {
-        kB.alloc(E * sizeof(K), s);
-        vB.alloc(E * 4, s);
-        inB = radix_sort<K, 1>(kA.as<K>(), vA.as<uint32_t>(), kB.as<K>(), vB.as<uint32_t>(), E, P->rec_shifts,
-                            bases.as<uint32_t>(), P->tune.record_sort_tile, s);
+        if (pk) {
+            kB.alloc(E * 8, s);
+            inB = radix_sort_packed(kA.as<uint64_t>(), kB.as<uint64_t>(), E, P->rec_shifts, P->pay_bits,
+                                    bases.as<uint32_t>(), P->tune.record_sort_tile, s);
+        } else {
+            kB.alloc(E * sizeof(K), s);
+            vB.alloc(E * 4, s);
+            inB = radix_sort<K, 1>(kA.as<K>(), vA.as<uint32_t>(), kB.as<K>(), vB.as<uint32_t>(), E, P->rec_shifts,
+                                bases.as<uint32_t>(), P->tune.record_sort_tile, s);
+        }
     }
     outK = std::move(inB ? kB : kA);
     outV = std::move(inB ? vB : vA);
+}
+
+// How the scans read the plan's sorted records: packed words (kp) or a key
+// array (kp) and a payload array (vp).
+template <class K, bool PK>
+RecSrc<K, PK> rec_src(const Plan *P, const void *kp, const uint32_t *vp) {
+    RecSrc<K, PK> r{};
+    if (PK) {
+        r.packed = static_cast<const uint64_t *>(kp);
+        r.pay_bits = P->pay_bits;  // (label payloads unless the records carry weights)
+    } else {
+        r.keys = static_cast<const K *>(kp);
+        r.vals = vp;
+    }
+    return r;
 }
 
 void records_for_call(Plan *P, hipStream_t s, DevBuf &k, DevBuf &v, const void **kp, const uint32_t **vp) {
@@ -1221,11 +1325,10 @@ void scatter(const T *src, const uint32_t *idx, T *dst, uint64_t n, hipStream_t 
     launch("permute_out", s, [&] { scatter_kernel<T><<<grid_for(n), kBlock, 0, s>>>(src, idx, dst, n); });
 }
 
-template <class K, class W, class V, int OP, bool INL>
-void forward_run(Plan *P, const void *kp, const uint32_t *vp, const void *w, void *out, hipStream_t s) {
-    ForwardProblem<K, W, V, OP, INL> fp{};
-    fp.keys = static_cast<const K *>(kp);
-    fp.vals = vp;
+template <class K, class W, class V, int OP, bool INL, bool PK>
+void forward_run_pk(Plan *P, const void *kp, const uint32_t *vp, const void *w, void *out, hipStream_t s) {
+    ForwardProblem<K, W, V, OP, INL, PK> fp{};
+    fp.rec = rec_src<K, PK>(P, kp, vp);
     fp.w = static_cast<const W *>(w);
     fp.flag_shift = P->flag_shift;
     fp.nw = (uint64_t)P->nD;
@@ -1240,7 +1343,7 @@ void forward_run(Plan *P, const void *kp, const uint32_t *vp, const void *w, voi
     // m = 1: every query has exactly one record, so it is stored in place
     fp.q = part_dest<V>(P, true, P->nax == 0 ? res : P->part.as<V>());
     fp.d = PartDest<V>{};
-    using FP = ForwardProblem<K, W, V, OP, INL>;
+    using FP = ForwardProblem<K, W, V, OP, INL, PK>;
     if (P->tune.scan_items == 8 || sizeof(K) == 8)
         scan_launch<FP, 8>("forward_scan", fp, (uint64_t)P->E, P->scan_status.as<uint64_t>(), P->scan_words,
                            P->scan_ticket.as<uint32_t>(), s);
@@ -1248,6 +1351,12 @@ void forward_run(Plan *P, const void *kp, const uint32_t *vp, const void *w, voi
         scan_launch<FP, 16>("forward_scan", fp, (uint64_t)P->E, P->scan_status.as<uint64_t>(), P->scan_words,
                             P->scan_ticket.as<uint32_t>(), s);
     if (P->nax > 0) regroup<V, OP>(P, true, P->part.as<V>(), res, s);
+}
+
+template <class K, class W, class V, int OP, bool INL>
+void forward_run(Plan *P, const void *kp, const uint32_t *vp, const void *w, void *out, hipStream_t s) {
+    if (P->packed) forward_run_pk<K, W, V, OP, INL, true>(P, kp, vp, w, out, s);
+    else forward_run_pk<K, W, V, OP, INL, false>(P, kp, vp, w, out, s);
 }
 
 // Records that carry weights were built for one (op, weight dtype); the
@@ -1286,8 +1395,8 @@ void forward_dispatch(Plan *P, dom_agg_op op, dom_agg_dtype wdt, const void *kp,
 // keeping the partial aggregates of data records too, the regrouping of both
 // kinds by point (their totals), the records per ID and their offsets, the
 // IDs, and the broadcast of each ID's total along its run.
-template <class K, class W, class V, int OP>
-void records_run(Plan *P, const void *kp, const uint32_t *vp, const void *w, int64_t *ids, V *vals,
+template <class K, class W, class V, int OP, bool PK>
+void records_run_pk(Plan *P, const void *kp, const uint32_t *vp, const void *w, int64_t *ids, V *vals,
                  hipStream_t s) {
     const uint64_t nD = (uint64_t)P->nD, nQ = (uint64_t)P->nQ, n = (uint64_t)P->n, E = (uint64_t)P->E;
     const int nax = P->nax;
@@ -1299,9 +1408,8 @@ void records_run(Plan *P, const void *kp, const uint32_t *vp, const void *w, int
         tq.alloc(std::max<uint64_t>(slots ? (uint64_t)P->n_slots * nQ : E - P->E_D, 1) * sizeof(V), s);
         td.alloc(std::max<uint64_t>(slots ? (uint64_t)P->n_slots * nD : P->E_D, 1) * sizeof(V), s);
     }
-    ForwardProblem<K, W, V, OP, false> fp{};
-    fp.keys = static_cast<const K *>(kp);
-    fp.vals = vp;
+    ForwardProblem<K, W, V, OP, false, PK> fp{};
+    fp.rec = rec_src<K, PK>(P, kp, vp);
     fp.w = static_cast<const W *>(w);
     fp.flag_shift = -1;
     fp.nw = nD;
@@ -1315,7 +1423,7 @@ void records_run(Plan *P, const void *kp, const uint32_t *vp, const void *w, int
     fp.sm = P->slot_map();
     fp.q = part_dest<V>(P, true, nax == 0 ? totq.as<V>() : tq.as<V>());
     fp.d = part_dest<V>(P, false, nax == 0 ? totd.as<V>() : td.as<V>());
-    using FP = ForwardProblem<K, W, V, OP, false>;
+    using FP = ForwardProblem<K, W, V, OP, false, PK>;
     if (E > 0) {
         if (P->tune.scan_items == 8 || sizeof(K) == 8)
             scan_launch<FP, 8>("forward_scan", fp, E, P->scan_status.as<uint64_t>(), P->scan_words,
@@ -1369,6 +1477,13 @@ void records_run(Plan *P, const void *kp, const uint32_t *vp, const void *w, int
                                             s);
 }
 
+template <class K, class W, class V, int OP>
+void records_run(Plan *P, const void *kp, const uint32_t *vp, const void *w, int64_t *ids, V *vals,
+                 hipStream_t s) {
+    if (P->packed) records_run_pk<K, W, V, OP, true>(P, kp, vp, w, ids, vals, s);
+    else records_run_pk<K, W, V, OP, false>(P, kp, vp, w, ids, vals, s);
+}
+
 template <class K>
 void records_dispatch(Plan *P, dom_agg_op op, dom_agg_dtype wdt, const void *kp, const uint32_t *vp, const void *w,
                       int64_t *ids, void *vals, hipStream_t s) {
@@ -1391,11 +1506,10 @@ void records_dispatch(Plan *P, dom_agg_op op, dom_agg_dtype wdt, const void *kp,
     }
 }
 
-template <class K, class G>
-void backward_typed(Plan *P, const void *kp, const uint32_t *vp, const void *g, void *grad, hipStream_t s) {
-    BackwardProblem<K, G> bp{};
-    bp.keys = static_cast<const K *>(kp);
-    bp.vals = vp;
+template <class K, class G, bool PK>
+void backward_typed_pk(Plan *P, const void *kp, const uint32_t *vp, const void *g, void *grad, hipStream_t s) {
+    BackwardProblem<K, G, PK> bp{};
+    bp.rec = rec_src<K, PK>(P, kp, vp);
     bp.g = static_cast<const G *>(g);
     if (P->permuted && P->nQ > 0) {
         gather(static_cast<const G *>(g), P->qinv.as<uint32_t>(), P->perm.as<G>(), (uint64_t)P->nQ, s);
@@ -1407,12 +1521,18 @@ void backward_typed(Plan *P, const void *kp, const uint32_t *vp, const void *g, 
     bp.ng = (uint64_t)P->nQ;
     bp.E = (uint64_t)P->E;
     if (P->tune.scan_items == 8 || sizeof(K) == 8)
-        scan_launch<BackwardProblem<K, G>, 8>("backward_scan", bp, (uint64_t)P->E, P->scan_status.as<uint64_t>(),
+        scan_launch<BackwardProblem<K, G, PK>, 8>("backward_scan", bp, (uint64_t)P->E, P->scan_status.as<uint64_t>(),
                                               P->scan_words, P->scan_ticket.as<uint32_t>(), s);
     else
-        scan_launch<BackwardProblem<K, G>, 16>("backward_scan", bp, (uint64_t)P->E, P->scan_status.as<uint64_t>(),
+        scan_launch<BackwardProblem<K, G, PK>, 16>("backward_scan", bp, (uint64_t)P->E, P->scan_status.as<uint64_t>(),
                                                P->scan_words, P->scan_ticket.as<uint32_t>(), s);
     if (P->nax > 0) regroup<G, OP_SUM>(P, false, P->part.as<G>(), res, s);
+}
+
+template <class K, class G>
+void backward_typed(Plan *P, const void *kp, const uint32_t *vp, const void *g, void *grad, hipStream_t s) {
+    if (P->packed) backward_typed_pk<K, G, true>(P, kp, vp, g, grad, s);
+    else backward_typed_pk<K, G, false>(P, kp, vp, g, grad, s);
 }
 
 // Runs `body` directly, or through the plan's HIP graph in DOM_AGG_GRAPH mode.
@@ -1503,6 +1623,7 @@ void tune_plan(Plan *P, hipStream_t s) {
     int best_tile = P->tune.record_sort_tile;
     for (int tile : {2048, 4096, 8192, 16384}) {
         if (effective_tile<uint32_t, 1>(tile) != tile || (P->key64 && tile == 16384)) continue;
+        if (P->packed && tile != 4096 && tile != 8192) continue;  // (the packed sort's two tile shapes)
         P->tune.record_sort_tile = tile;
         DevBuf k, v;
         const float ms = time_ms(s, [&] {
@@ -1899,6 +2020,7 @@ dom_agg_status dom_agg_plan_get_info(dom_agg_plan_t plan, dom_agg_plan_info *inf
         info->workspace_bytes = plan->workspace();
         info->le_mask = plan->le_mask;
         info->graph_captures = plan->graph_captures;
+        info->record_bytes = plan->packed ? 8 : (plan->key64 ? 8 : 4) + 4;
         info->basic = plan->basic ? 1 : 0;
     });
 }

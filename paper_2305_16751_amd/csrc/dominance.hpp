@@ -527,7 +527,23 @@ struct EmitArgs {
     // has bit flag_shift set (above every digit the sort looks at)
     const uint32_t *wv;
     int flag_shift;
+    // packed records (pk_a non-null): one 64-bit word per record, the key
+    // shifted up by pk_shift above the payload; written to pk_a (to pk_b for
+    // classes whose region lives in buffer B) instead of the key and payload
+    // arrays
+    uint64_t *pk_a, *pk_b;
+    int pk_shift;
+    bool pk_labels;  // the payload is a flagged label (else 32 raw bits)
 };
+
+// A record as one 64-bit word: key above pay_bits payload bits.  A flagged
+// label keeps its query flag in the top payload bit (see RecSrc).
+template <class K>
+__device__ __forceinline__ uint64_t pack_record(K key, uint32_t pay, int pay_bits, bool labels) {
+    uint64_t p = pay;
+    if (labels && (pay & kQueryFlag)) p = (1ull << (pay_bits - 1)) | (pay & ~kQueryFlag);
+    return ((uint64_t)key << pay_bits) | p;
+}
 
 // Sum of the 16-bit fields of `packed` below field q (q <= 4).
 __device__ __forceinline__ uint32_t packed_prefix(uint64_t packed, int q) {
@@ -1240,7 +1256,23 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(EmitArgs a, K *__restrict__
         nkhi = s_next[1];
         // the next chunk's points, loaded while this chunk's records are stored
         if (cn < nchunks) prefetch(cn, nklo, nkhi);
-        if constexpr (!CLS) {
+        if (a.pk_a) {
+            // packed records: one 64-bit word per record
+            for (uint32_t i = threadIdx.x; i < nrec; i += BLOCK) {
+                uint64_t dst = o0 + i;
+                uint64_t *out = a.pk_a;
+                if constexpr (CLS) {
+                    int q = 0;
+#pragma unroll
+                    for (int t = 1; t < kMaxClasses; ++t)
+                        if (t < a.ncls && i >= packed_prefix(tot, t)) q = t;
+                    dst = s_cdst[q] + i;
+                    if (!((cls_info >> (16 * q + 8)) & 1u)) out = a.pk_b;
+                }
+                if (dst >= a.E) continue;  // only if the class totals were wrong
+                out[dst] = pack_record(s_keys[i], s_pay[i], a.pk_shift, a.pk_labels);
+            }
+        } else if constexpr (!CLS) {
             for (uint32_t i = threadIdx.x; i < nrec; i += BLOCK) {
                 keys_a[o0 + i] = s_keys[i];
                 vals_a[o0 + i] = s_pay[i];
@@ -1393,6 +1425,38 @@ __device__ __forceinline__ Out acc_out(A a) {
     else return (Out)a;
 }
 
+// The sorted records as the scans read them: two arrays (key, 32-bit
+// payload), or one array of packed 64-bit words (key above pay_bits payload
+// bits).  Packed label payloads (plan records) keep the query flag in their
+// top payload bit and are returned in the 32-bit form (kQueryFlag | row);
+// packed weight payloads (records that carry weights) take all 32 bits.
+// PK (the layout) and LABELS (the payload kind) are compile-time choices:
+// a run-time branch inside the scans' load loops made the compiler wait for
+// every load before the next one was issued.
+template <class K, bool PK>
+struct RecSrc {
+    const K *keys;
+    const uint32_t *vals;
+    const uint64_t *packed;
+    int pay_bits;   // packed: payload bits (32 for weight payloads)
+    template <bool LABELS = true>
+    __device__ __forceinline__ void get(uint64_t i, K &k, uint32_t &pay) const {
+        if constexpr (PK) {
+            const uint64_t w = packed[i];
+            k = (K)(w >> pay_bits);
+            if constexpr (LABELS) {
+                const uint32_t row = (uint32_t)w & ((1u << (pay_bits - 1)) - 1u);
+                pay = ((w >> (pay_bits - 1)) & 1u) ? (kQueryFlag | row) : row;
+            } else {
+                pay = (uint32_t)w;
+            }
+        } else {
+            k = keys[i];
+            pay = vals[i];
+        }
+    }
+};
+
 // Where a scan puts the partial aggregates of one kind of point (queries in
 // the forward, data in the backward; both in the forward that also reports
 // data totals).  part == null: not stored.
@@ -1429,15 +1493,14 @@ struct PartDest {
 // INL: the records carry the weights (a data record's payload is its weight
 // bits, a query record's key has bit flag_shift set and its payload is the
 // query's row), so the scan reads them in sequence instead of gathering.
-template <class K, class W, class Out, int OP, bool INL = false>
+template <class K, class W, class Out, int OP, bool INL = false, bool PK = false>
 struct ForwardProblem {
     using V = typename AccumOf<Out, OP>::type;
     struct Raw {
         K key;
         uint32_t payload;
     };
-    const K *keys;
-    const uint32_t *vals;
+    RecSrc<K, PK> rec;
     const W *w;  // unused for COUNT and INL
     PartDest<Out> q, d;
     uint64_t nw;     // weights (|D|): payloads are checked against it
@@ -1450,7 +1513,11 @@ struct ForwardProblem {
     }
     __device__ V identity() const { return Monoid<V, OP>::identity(); }
     __device__ V combine(V a, V b) const { return Monoid<V, OP>::combine(a, b); }
-    __device__ Raw load(uint64_t i) const { return Raw{keys[i], vals[i]}; }
+    __device__ Raw load(uint64_t i) const {
+        Raw r;
+        rec.template get<!INL>(i, r.key, r.payload);  // (records carrying weights hold raw weight bits)
+        return r;
+    }
     __device__ bool head(const Raw &prev, const Raw &cur) const {
         if constexpr (INL) return ((prev.key ^ cur.key) & ~(K(1) << flag_shift)) != K(0);
         else return prev.key != cur.key;
@@ -1484,15 +1551,14 @@ struct ForwardProblem {
 // coordinates put queries first, so they come before the data record and are
 // not counted).  Those partials go to the data point's places of the
 // regrouping (internal numbering).
-template <class K, class G>
+template <class K, class G, bool PK = false>
 struct BackwardProblem {
     using V = typename AccumOf<G, OP_SUM>::type;
     struct Raw {
         K key;
         uint32_t payload;
     };
-    const K *keys;
-    const uint32_t *vals;
+    RecSrc<K, PK> rec;
     const G *g;
     PartDest<G> d;
     uint64_t ng;  // |Q|
@@ -1502,8 +1568,9 @@ struct BackwardProblem {
     __device__ V identity() const { return Monoid<V, OP_SUM>::identity(); }
     __device__ V combine(V a, V b) const { return Monoid<V, OP_SUM>::combine(a, b); }
     __device__ Raw load(uint64_t i) const {
-        const uint64_t q = E - 1 - i;
-        return Raw{keys[q], vals[q]};
+        Raw r;
+        rec.template get<true>(E - 1 - i, r.key, r.payload);
+        return r;
     }
     __device__ bool head(const Raw &prev, const Raw &cur) const { return prev.key != cur.key; }
     __device__ V value(const Raw &, bool, const Raw &cur, uint64_t) const {

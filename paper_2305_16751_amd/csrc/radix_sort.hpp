@@ -145,29 +145,35 @@ struct DigitWord {
 // instantiation (0: per-point coordinate sorts, 1: the sort of the expanded
 // records) so the two show up separately in profiles.  VT: the payload type
 // (u32, or u64 for the last-axis sort that carries each point's rank).
-template <class K, class S, int BLOCK, int ITEMS, int ROLE = 0, class VT = uint32_t>
+// HAS_VAL = false: keys only (a record packed into one word: its digits sit
+// at `shift` within the word), vin / vout unused.  RBITS: the digit width
+// (status words and digit bases are [2^RBITS] per tile / pass).
+template <class K, class S, int BLOCK, int ITEMS, int ROLE = 0, class VT = uint32_t, bool HAS_VAL = true,
+          int RBITS = kRadixBits>
 __global__ __launch_bounds__(BLOCK) void onesweep_kernel(
     const K *__restrict__ kin, const VT *__restrict__ vin, K *__restrict__ kout,
     VT *__restrict__ vout, uint32_t n, int shift, const uint32_t *__restrict__ digit_base,
     S *__restrict__ status, uint32_t *__restrict__ ticket) {
     constexpr int TILE = BLOCK * ITEMS;
     constexpr int WAVES = BLOCK / kWave;
+    constexpr int RADIX = 1 << RBITS;
     using W = DigitWord<S>;
-    static_assert(BLOCK >= kRadix, "one thread per digit");
+    static_assert(BLOCK >= RADIX, "one thread per digit");
+    static_assert(RBITS >= 4 && RBITS <= 10, "");
     static_assert(ITEMS <= 32, "");
 
     __shared__ union {
         K keys[TILE];
         VT vals[TILE];
     } s_stage;
-    __shared__ uint32_t s_whist[WAVES][kRadix];  // counts, then exclusive over waves
-    __shared__ uint32_t s_dstart[kRadix];        // tile-local start of each digit
-    __shared__ uint32_t s_goff[kRadix];          // global start minus local start
+    __shared__ uint32_t s_whist[WAVES][RADIX];  // counts, then exclusive over waves
+    __shared__ uint32_t s_dstart[RADIX];        // tile-local start of each digit
+    __shared__ uint32_t s_goff[RADIX];          // global start minus local start
     __shared__ uint32_t s_tmp[WAVES];
     __shared__ uint32_t s_tile;
 
     const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
-    for (int i = tid; i < WAVES * kRadix; i += BLOCK) (&s_whist[0][0])[i] = 0;
+    for (int i = tid; i < WAVES * RADIX; i += BLOCK) (&s_whist[0][0])[i] = 0;
     if (tid == 0) s_tile = atomicAdd(ticket, 1u);
     __syncthreads();
     const uint32_t tile = s_tile;
@@ -183,9 +189,9 @@ __global__ __launch_bounds__(BLOCK) void onesweep_kernel(
         const uint64_t idx = wbase + (uint64_t)i * kWave + lane;
         if (idx < n) {
             key[i] = kin[idx];
-            val[i] = vin[idx];
+            if constexpr (HAS_VAL) val[i] = vin[idx];
         } else {
-            key[i] = ~K(0);  // digit 255 at every shift: sorts after all real keys of the tile
+            key[i] = ~K(0);  // the largest digit at every shift: sorts after all real keys of the tile
             val[i] = VT(0);
         }
     }
@@ -193,8 +199,8 @@ __global__ __launch_bounds__(BLOCK) void onesweep_kernel(
     const uint64_t below_mask = lanemask_lt();
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
-        const uint32_t d = (uint32_t)(key[i] >> shift) & (kRadix - 1);
-        const uint64_t peers = match_digit<kRadixBits>(d);
+        const uint32_t d = (uint32_t)(key[i] >> shift) & (RADIX - 1);
+        const uint64_t peers = match_digit<RBITS>(d);
         const uint32_t below = (uint32_t)__popcll(peers & below_mask);
         const uint32_t cnt = s_whist[wave][d];
         loc[i] = cnt + below;
@@ -203,18 +209,18 @@ __global__ __launch_bounds__(BLOCK) void onesweep_kernel(
     __syncthreads();
 
     uint32_t count = 0;
-    if (tid < kRadix) {
+    if (tid < RADIX) {
 #pragma unroll
         for (int w = 0; w < WAVES; ++w) {
             const uint32_t c = s_whist[w][tid];
             s_whist[w][tid] = count;
             count += c;
         }
-        store_agent(&status[(uint64_t)tile * kRadix + tid],
+        store_agent(&status[(uint64_t)tile * RADIX + tid],
                     W::make(tile == 0 ? kFlagInclusive : kFlagAggregate, count));
     }
-    const uint32_t dstart = block_excl_sum<BLOCK>(tid < kRadix ? count : 0u, s_tmp, nullptr);
-    if (tid < kRadix) {
+    const uint32_t dstart = block_excl_sum<BLOCK>(tid < RADIX ? count : 0u, s_tmp, nullptr);
+    if (tid < RADIX) {
         s_dstart[tid] = dstart;
         uint32_t excl = 0;
         if (tile > 0) {
@@ -228,20 +234,20 @@ __global__ __launch_bounds__(BLOCK) void onesweep_kernel(
                 S w[kDepth];
 #pragma unroll
                 for (int k = 0; k < kDepth; ++k)
-                    w[k] = (t - k >= 0) ? load_agent(&status[(uint64_t)(t - k) * kRadix + tid]) : S(0);
+                    w[k] = (t - k >= 0) ? load_agent(&status[(uint64_t)(t - k) * RADIX + tid]) : S(0);
 #pragma unroll
                 for (int k = 0; k < kDepth; ++k) {
                     if (done || t - k < 0) continue;
                     while (W::flag(w[k]) == 0) {
                         __builtin_amdgcn_s_sleep(2);
-                        w[k] = load_agent(&status[(uint64_t)(t - k) * kRadix + tid]);
+                        w[k] = load_agent(&status[(uint64_t)(t - k) * RADIX + tid]);
                     }
                     excl += W::count(w[k]);
                     done = W::flag(w[k]) == kFlagInclusive;
                 }
                 t -= kDepth;
             }
-            store_agent(&status[(uint64_t)tile * kRadix + tid], W::make(kFlagInclusive, excl + count));
+            store_agent(&status[(uint64_t)tile * RADIX + tid], W::make(kFlagInclusive, excl + count));
         }
         s_goff[tid] = digit_base[tid] + excl - dstart;
     }
@@ -249,7 +255,7 @@ __global__ __launch_bounds__(BLOCK) void onesweep_kernel(
 
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
-        const uint32_t d = (uint32_t)(key[i] >> shift) & (kRadix - 1);
+        const uint32_t d = (uint32_t)(key[i] >> shift) & (RADIX - 1);
         const uint32_t lp = s_dstart[d] + s_whist[wave][d] + loc[i];
         s_stage.keys[lp] = key[i];
         loc[i] = lp;
@@ -261,19 +267,21 @@ __global__ __launch_bounds__(BLOCK) void onesweep_kernel(
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t p = (uint32_t)(i * BLOCK + tid);
         const K k = s_stage.keys[p];
-        const uint32_t d = (uint32_t)(k >> shift) & (kRadix - 1);
+        const uint32_t d = (uint32_t)(k >> shift) & (RADIX - 1);
         const uint32_t g = s_goff[d] + p;
         gpos[i] = g;
         if (g < n) kout[g] = k;
     }
-    __syncthreads();
+    if constexpr (HAS_VAL) {
+        __syncthreads();
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i) s_stage.vals[loc[i]] = val[i];
-    __syncthreads();
+        for (int i = 0; i < ITEMS; ++i) s_stage.vals[loc[i]] = val[i];
+        __syncthreads();
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        const uint32_t p = (uint32_t)(i * BLOCK + tid);
-        if (gpos[i] < n) vout[gpos[i]] = s_stage.vals[p];
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t p = (uint32_t)(i * BLOCK + tid);
+            if (gpos[i] < n) vout[gpos[i]] = s_stage.vals[p];
+        }
     }
 }
 
