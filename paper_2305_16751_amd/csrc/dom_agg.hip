@@ -258,6 +258,16 @@ void require_gfx950(int *device) {
 
 // DOM_AGG_PACK=0 keeps records as separate key and payload arrays (for
 // measurement); packing is on otherwise.
+// Whether the record sort's digit histograms come from a streaming pass over
+// the emitted records (else from inside the flat map): `dflt`, unless
+// DOM_AGG_SEP_HIST=0 or =1 says otherwise (for measurement).
+bool separate_histograms(bool dflt) {
+    const char *e = std::getenv("DOM_AGG_SEP_HIST");
+    if (e && e[0] == '0') return false;
+    if (e && e[0] == '1') return true;
+    return dflt;
+}
+
 bool packing_enabled() {
     static const bool on = [] {
         const char *e = std::getenv("DOM_AGG_PACK");
@@ -973,6 +983,23 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
              (unsigned long long)kMaxRecords);
 }
 
+// Digit passes of the record key whose digit is skewed: those holding the
+// top bits of a tree-node field (node ids at level j have their leading 1 at
+// bit j, so most ids are small) or instance bits.
+uint32_t skewed_passes(const Plan *P) {
+    uint32_t skew = 0;
+    auto mark = [&](int lo, int hi) {  // bits [lo, hi)
+        for (int p = 0; p < kMaxPasses; ++p)
+            if (p * kRadixBits < hi && (p + 1) * kRadixBits > lo) skew |= 1u << p;
+    };
+    for (int a = 0; a < P->nax; ++a) {
+        const int top = P->field_shift[a] + P->Lmax[a];  // one past the field's top bit
+        if (P->Lmax[a] > 0) mark(top - 1, top);
+    }
+    if (P->batched) mark(P->inst_shift, P->inst_shift + P->inst_bits);
+    return skew;
+}
+
 // ---------------------------------------------------------------------------
 // The flat map and the record sort.  With `probe`, the histogram is read back
 // to find the live radix passes (stored in the plan); otherwise the stored
@@ -1017,13 +1044,21 @@ void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &ou
     // thread per tree node, instead of one update per record in the flat map
     // (not with <= on the first axis: the rank CDFs are of the unshifted ranks)
     const bool node_hist = cls && P->cdf_d.p && P->m == 2 && !(P->le_mask & 1u);
+    // m >= 3 with one instance: from the emitted records, in a streaming pass
+    // after the flat map (measured faster there: 1.3 + 1.8 ms vs 3.6 ms for
+    // |D| = |Q| = 2^20 at m = 3); otherwise inside the flat map's per-record
+    // loop, where it hides behind the walk's latency (batched m = 2 and m = 4
+    // measured faster that way).  DOM_AGG_SEP_HIST=0 / 1 overrides.
+    const bool sep_hist = !node_hist && separate_histograms(P->nax >= 2 && !P->batched);
+    const bool emit_hist = !node_hist && !sep_hist;
     // the flat map's workgroups: as many as are resident at once (each takes
     // a fixed share of the chunks)
     unsigned grid = 1;
     per_nax([&](auto nax_c) {
         constexpr int NAX = decltype(nax_c)::value;
-        if (node_hist) grid = resident_grid(emit_kernel<K, NAX, kBlock, EITEMS, true, false>, nchunks);
+        if (cls && !emit_hist) grid = resident_grid(emit_kernel<K, NAX, kBlock, EITEMS, true, false>, nchunks);
         else if (cls) grid = resident_grid(emit_kernel<K, NAX, kBlock, EITEMS, true>, nchunks);
+        else if (!emit_hist) grid = resident_grid(emit_kernel<K, NAX, kBlock, EITEMS, false, false>, nchunks);
         else grid = resident_grid(emit_kernel<K, NAX, kBlock, EITEMS, false>, nchunks);
     });
     DevBuf chunk_k;
@@ -1134,6 +1169,7 @@ void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &ou
     // (packed records: the key and payload arrays are not written)
     K *ka = pk ? nullptr : kA.as<K>(), *kb = pk ? nullptr : kB.as<K>();
     uint32_t *va = vA.as<uint32_t>(), *vb = vB.as<uint32_t>();
+    if (sep_hist) a.hist_part = nullptr;  // (histograms after the flat map)
     per_nax([&](auto nax_c) {
         constexpr int NAX = decltype(nax_c)::value;
         launch("flatmap_emit", s, [&] {
@@ -1141,12 +1177,44 @@ void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &ou
                 emit_kernel<K, NAX, kBlock, EITEMS, true, false><<<grid, kBlock, 0, s>>>(a, ka, va, kb, vb);
             else if (cls)
                 emit_kernel<K, NAX, kBlock, EITEMS, true><<<grid, kBlock, 0, s>>>(a, ka, va, kb, vb);
+            else if (!a.hist_part)
+                emit_kernel<K, NAX, kBlock, EITEMS, false, false><<<grid, kBlock, 0, s>>>(a, ka, va, nullptr, nullptr);
             else
                 emit_kernel<K, NAX, kBlock, EITEMS, false><<<grid, kBlock, 0, s>>>(a, ka, va, nullptr, nullptr);
         });
     });
-    if (node_hist) reduce_hist(npart.as<uint32_t>(), (int)ngrid, rows, counts.as<uint32_t>(), bases.as<uint32_t>(), s);
-    else reduce_hist(part.as<uint32_t>(), (int)grid, rows, counts.as<uint32_t>(), bases.as<uint32_t>(), s);
+    if (node_hist) {
+        reduce_hist(npart.as<uint32_t>(), (int)ngrid, rows, counts.as<uint32_t>(), bases.as<uint32_t>(), s);
+    } else if (sep_hist) {
+        RecHistArgs h{};
+        h.pk[0] = pk ? kA.as<uint64_t>() : nullptr;
+        h.pk[1] = pk ? kB.as<uint64_t>() : nullptr;
+        h.keys[0] = pk ? nullptr : kA.p;
+        h.keys[1] = pk ? nullptr : kB.p;
+        h.E = E;
+        h.ncls = P->ncls;
+        for (int q = 0; q < kMaxClasses; ++q) {
+            h.cls_base[q] = a.cls_base[q];
+            h.cls_passes[q] = P->cls_passes[q];
+            h.cls_row0[q] = P->cls_row0[q];
+            h.cls_in_b[q] = (P->cls_passes[q] & 1) ? 0 : 1;  // (see EmitArgs: odd-pass classes start in A)
+        }
+        h.passes = passes;
+        h.pay_bits = P->pay_bits;
+        h.rows = rows;
+        h.skew = skewed_passes(P);
+        const unsigned hgrid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(ceil_div(E, kBlock * 4), 1024));
+        DevBuf hpart;
+        hpart.alloc((size_t)hgrid * rows * kRadix * 4, s);
+        h.hist_part = hpart.as<uint32_t>();
+        launch("record_hist", s, [&] {
+            if (pk) record_hist_kernel<K, true><<<hgrid, kBlock, 0, s>>>(h);
+            else record_hist_kernel<K, false><<<hgrid, kBlock, 0, s>>>(h);
+        });
+        reduce_hist(hpart.as<uint32_t>(), (int)hgrid, rows, counts.as<uint32_t>(), bases.as<uint32_t>(), s);
+    } else {
+        reduce_hist(part.as<uint32_t>(), (int)grid, rows, counts.as<uint32_t>(), bases.as<uint32_t>(), s);
+    }
     if (probe) {
         const size_t cb = (size_t)rows * kRadix * 4;
         uint32_t *h = static_cast<uint32_t *>(hs->get(cb + 12));

@@ -783,6 +783,91 @@ __device__ __forceinline__ void hist_add_rows(uint32_t *s_hist, K key, bool vali
     }
 }
 
+// The record sort's digit histograms from the emitted records, in one
+// streaming pass (instead of inside the flat map's per-record loop): every
+// record of class q (its region of buffer A or B) adds the digits of its key
+// for the class's passes to rows row0[q] .. row0[q] + passes[q] - 1.
+// Without classes all records are in A, with `passes` rows.
+struct RecHistArgs {
+    const uint64_t *pk[2];  // packed records in buffers A and B, or null
+    const void *keys[2];    // keys (K) in A and B when not packed
+    uint64_t E;
+    int ncls;               // 1: no classes
+    uint64_t cls_base[kMaxClasses];
+    int cls_passes[kMaxClasses];
+    int cls_row0[kMaxClasses];
+    int cls_in_b[kMaxClasses];  // the region lives in buffer B
+    int passes;             // without classes; with classes the largest class's
+    int pay_bits;
+    int rows;
+    uint32_t skew;          // bit p: pass p's digit is skewed (holds a field's top bits)
+    uint32_t *hist_part;    // [gridDim.x][rows][256]
+};
+
+// hist_add_rows where only the passes in `skew` aggregate equal digits over
+// the wavefront first; the spread digits of the other passes take one LDS
+// atomic per lane.
+template <class K>
+__device__ __forceinline__ void hist_add_rows_skew(uint32_t *s_hist, K key, bool valid, int row0, int np,
+                                                   int max_np, uint32_t skew) {
+    const int lane = lane_id();
+    for (int p = 0; p < max_np; ++p) {
+        const bool v = valid && p < np;
+        const uint32_t idx = (uint32_t)(row0 + p) * kRadix + ((uint32_t)(key >> (kRadixBits * p)) & (kRadix - 1));
+        if (!((skew >> p) & 1u)) {
+            if (v) atomicAdd(&s_hist[idx], 1u);
+            continue;
+        }
+        const uint64_t act = __ballot(v);
+        if (act == 0) continue;
+        const int leader = __ffsll((unsigned long long)act) - 1;
+        const uint32_t i0 = read_lane_u32(idx, leader);
+        const uint64_t same = __ballot(v && idx == i0);
+        if (lane == leader) atomicAdd(&s_hist[i0], (uint32_t)__popcll(same));
+        if (v && idx != i0) atomicAdd(&s_hist[idx], 1u);
+    }
+}
+
+template <class K, bool PK>
+__global__ __launch_bounds__(256) void record_hist_kernel(RecHistArgs a) {
+    __shared__ uint32_t s_hist[26 * kRadix];
+    for (int i = threadIdx.x; i < a.rows * kRadix; i += blockDim.x) s_hist[i] = 0;
+    __syncthreads();
+    // every lane of a wavefront runs the same iterations (the histogram adds
+    // are wavefront operations); U records per lane, loads issued together
+    constexpr int U = 4;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x * U;
+    const uint64_t wbase = ((uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(uint64_t)(kWave - 1))) * U;
+    const int lane = lane_id();
+    for (uint64_t b = wbase; b < a.E; b += stride) {
+        K key[U];
+        int q[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t i0 = b + (uint64_t)u * kWave + lane;
+            const uint64_t i = i0 < a.E ? i0 : a.E - 1;
+            int c = 0;
+#pragma unroll
+            for (int t = 1; t < kMaxClasses; ++t)
+                if (t < a.ncls && i >= a.cls_base[t]) c = t;
+            q[u] = c;
+            const int buf = a.ncls > 1 ? a.cls_in_b[c] : 0;
+            if constexpr (PK) key[u] = (K)(a.pk[buf][i] >> a.pay_bits);
+            else key[u] = static_cast<const K *>(a.keys[buf])[i];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool valid = b + (uint64_t)u * kWave + lane < a.E;
+            const int c = q[u];
+            const int row0 = a.ncls > 1 ? a.cls_row0[c] : 0;
+            const int np = a.ncls > 1 ? a.cls_passes[c] : a.passes;
+            hist_add_rows_skew(s_hist, key[u], valid, row0, np, a.passes, a.skew);
+        }
+    }
+    __syncthreads();
+    hist_flush(s_hist, a.hist_part, a.rows);
+}
+
 // Exclusive sum of packed 16-bit counters over a block (each field's block
 // total must stay below 2^16); *total gets the packed block sums.
 template <int BLOCK>
