@@ -256,6 +256,17 @@ void require_gfx950(int *device) {
     *device = dev;
 }
 
+// DOM_AGG_DIGIT_BITS=7 or 8 fixes the record sort's digit width (for
+// measurement and tests; the tuner then searches tiles only, under keys of
+// their own); 0 when unset.
+int forced_digit_bits() {
+    const char *e = std::getenv("DOM_AGG_DIGIT_BITS");
+    if (!e || !e[0]) return 0;
+    const int v = std::atoi(e);
+    if (v != 7 && v != 8) fail(DOM_AGG_EINVAL, "DOM_AGG_DIGIT_BITS must be 7 or 8 (got \"%s\")", e);
+    return v;
+}
+
 // DOM_AGG_PACK=0 keeps records as separate key and payload arrays (for
 // measurement); packing is on otherwise.
 // Whether the record sort's digit histograms come from a streaming pass over
@@ -352,6 +363,7 @@ struct dom_agg_plan_s {
     int inst_shift = 0;
     int64_t E = 0, E_D = 0;
     std::vector<int> rec_shifts;  // radix passes the record sort runs (without classes)
+    int rbits = kRadixBits;       // the record sort's digit width (7 or 8; chosen by the tuner)
     // key-length classes of the record sort (ncls = 1: one sort over all records)
     int ncls = 1, cls_c0 = 0;
     int cls_passes[kMaxClasses] = {0, 0, 0, 0};
@@ -484,8 +496,14 @@ void clear_lookback(uint64_t *status, uint64_t words, uint32_t *ticket, hipStrea
 // ---------------------------------------------------------------------------
 // Radix sort driver.
 
-template <class K, int ROLE>
+template <class K, int ROLE, int RB = kRadixBits>
 const char *onesweep_name(int tile) {
+    if constexpr (RB != kRadixBits) {
+        static_assert(ROLE == 1 && RB == 7, "7-bit digits: record sort only");
+        static const char *n7[2][2] = {{"onesweep_records_u32_t4096_d7", "onesweep_records_u32_t8192_d7"},
+                                       {"onesweep_records_u64_t4096_d7", "onesweep_records_u64_t8192_d7"}};
+        return n7[sizeof(K) == 8][tile == 8192];
+    }
     static const char *names[2][2][3] = {
         {{"onesweep_points_u32_t2048", "onesweep_points_u32_t4096", "onesweep_points_u32_t8192"},
          {"onesweep_points_u64_t2048", "onesweep_points_u64_t4096", "onesweep_points_u64_t8192"}},
@@ -496,15 +514,15 @@ const char *onesweep_name(int tile) {
     return names[ROLE][sizeof(K) == 8][ti];
 }
 
-template <class K, class S, int BLOCK, int ITEMS, int ROLE, class VT>
+template <class K, class S, int BLOCK, int ITEMS, int ROLE, class VT, int RB = kRadixBits>
 void onesweep_launch(const K *kin, const VT *vin, K *kout, VT *vout, uint32_t n,
                      int shift, const uint32_t *bases, S *status, uint32_t *ticket, hipStream_t s) {
     // (status and ticket arrive cleared: one clear serves all passes of a sort)
     constexpr int TILE = BLOCK * ITEMS;
     const unsigned tiles = (unsigned)ceil_div(n, TILE);
-    launch(onesweep_name<K, ROLE>(TILE), s, [&] {
-        onesweep_kernel<K, S, BLOCK, ITEMS, ROLE, VT><<<tiles, BLOCK, 0, s>>>(kin, vin, kout, vout, n, shift,
-                                                                          bases, status, ticket);
+    launch(onesweep_name<K, ROLE, RB>(TILE), s, [&] {
+        onesweep_kernel<K, S, BLOCK, ITEMS, ROLE, VT, true, RB><<<tiles, BLOCK, 0, s>>>(
+            kin, vin, kout, vout, n, shift, bases, status, ticket);
     });
 }
 
@@ -517,11 +535,17 @@ int effective_tile(int tile) {
     return tile;
 }
 
-template <class K, class S, int ROLE, class VT>
+template <class K, class S, int ROLE, class VT, int RB = kRadixBits>
 void onesweep_dispatch(int tile, const K *kin, const VT *vin, K *kout, VT *vout, uint32_t n,
                        int shift, const uint32_t *bases, void *status, uint32_t *ticket, hipStream_t s) {
     S *st = static_cast<S *>(status);
-    if constexpr (sizeof(VT) == 8) {
+    if constexpr (RB != kRadixBits) {
+        // 7-bit digits: the two tile shapes the tuner tries with them
+        if (tile == 8192)
+            onesweep_launch<K, S, 512, 16, ROLE, VT, RB>(kin, vin, kout, vout, n, shift, bases, st, ticket, s);
+        else
+            onesweep_launch<K, S, 256, 16, ROLE, VT, RB>(kin, vin, kout, vout, n, shift, bases, st, ticket, s);
+    } else if constexpr (sizeof(VT) == 8) {
         // 64-bit payloads: one tile shape
         onesweep_launch<K, S, 256, 16, ROLE, VT>(kin, vin, kout, vout, n, shift, bases, st, ticket, s);
     } else if (tile == 2048) {
@@ -539,12 +563,16 @@ void onesweep_dispatch(int tile, const K *kin, const VT *vin, K *kout, VT *vout,
 }
 
 // Sorts (kA, vA) by the listed digit shifts; returns true when the result
-// ended up in (kB, vB).  bases: [passes][256] (pass p at shift 8p).
+// ended up in (kB, vB).  bases: [passes][256] (pass p at shift rb * p).
+// rb: digit width, 8, or 7 for the record sort (tiles 4096 and 8192).
 template <class K, int ROLE, class VT = uint32_t>
 bool radix_sort(K *kA, VT *vA, K *kB, VT *vB, uint64_t n, const std::vector<int> &shifts,
-                const uint32_t *bases, int tile, hipStream_t s) {
+                const uint32_t *bases, int tile, hipStream_t s, int rb = kRadixBits) {
     if (n == 0 || shifts.empty()) return false;
+    if (rb != kRadixBits && (ROLE != 1 || sizeof(VT) != 4 || rb != 7))
+        fail(DOM_AGG_EHIP, "internal: %d-bit digits are for the record sort only", rb);
     tile = sizeof(VT) == 8 ? 4096 : effective_tile<K, ROLE>(tile);
+    if (rb != kRadixBits) tile = tile == 8192 ? 8192 : 4096;
     const bool narrow = n < (1ull << 30);  // every digit count fits 30 bits
     // every pass gets its own look-back words (the tile count of the tile
     // shape the dispatch launches: TILE == tile) and, after all of them, its
@@ -562,14 +590,21 @@ bool radix_sort(K *kA, VT *vA, K *kB, VT *vB, uint64_t n, const std::vector<int>
         const VT *vi = inB ? vB : vA;
         K *ko = inB ? kA : kB;
         VT *vo = inB ? vA : vB;
-        const uint32_t *b = bases + (sh / kRadixBits) * kRadix;
+        const uint32_t *b = bases + (sh / rb) * kRadix;
         void *st = status.as<uint64_t>() + pass * pass_words;
-        if (narrow)
-            onesweep_dispatch<K, uint32_t, ROLE, VT>(tile, ki, vi, ko, vo, (uint32_t)n, sh, b, st, tickets + pass,
-                                                 s);
-        else
-            onesweep_dispatch<K, uint64_t, ROLE, VT>(tile, ki, vi, ko, vo, (uint32_t)n, sh, b, st, tickets + pass,
-                                                 s);
+        auto go = [&](auto s_c) {
+            using S = decltype(s_c);
+            if constexpr (ROLE == 1 && sizeof(VT) == 4) {
+                if (rb == 7) {
+                    onesweep_dispatch<K, S, ROLE, VT, 7>(tile, ki, vi, ko, vo, (uint32_t)n, sh, b, st,
+                                                         tickets + pass, s);
+                    return;
+                }
+            }
+            onesweep_dispatch<K, S, ROLE, VT>(tile, ki, vi, ko, vo, (uint32_t)n, sh, b, st, tickets + pass, s);
+        };
+        if (narrow) go(uint32_t{});
+        else go(uint64_t{});
         inB = !inB;
         ++pass;
     }
@@ -578,9 +613,11 @@ bool radix_sort(K *kA, VT *vA, K *kB, VT *vB, uint64_t n, const std::vector<int>
 }
 
 // Sorts packed 64-bit records (key above pay_bits payload bits) by the
-// listed key digit shifts; returns true when the result ended up in B.
+// listed key digit shifts (digits of rb = 7 or 8 bits); returns true when
+// the result ended up in B.
 bool radix_sort_packed(uint64_t *A, uint64_t *B, uint64_t n, const std::vector<int> &shifts, int pay_bits,
-                       const uint32_t *bases, int tile, hipStream_t s) {
+                       const uint32_t *bases, int tile, hipStream_t s, int rb = kRadixBits) {
+    if (rb != 7 && rb != 8) fail(DOM_AGG_EHIP, "internal: %d-bit digits", rb);
     if (n == 0 || shifts.empty()) return false;
     tile = tile == 4096 ? 4096 : 8192;
     const bool narrow = n < (1ull << 30);
@@ -595,14 +632,24 @@ bool radix_sort_packed(uint64_t *A, uint64_t *B, uint64_t n, const std::vector<i
     for (int sh : shifts) {
         const uint64_t *in = inB ? B : A;
         uint64_t *out = inB ? A : B;
-        const uint32_t *b = bases + (sh / kRadixBits) * kRadix;
+        const uint32_t *b = bases + (sh / rb) * kRadix;
         void *st = status.as<uint64_t>() + pass * pass_words;
         const unsigned tiles = (unsigned)ceil_div(n, (uint64_t)tile);
         const int shift = pay_bits + sh;
         auto go = [&](auto s_c) {
             using S = decltype(s_c);
             S *stw = static_cast<S *>(st);
-            if (tile == 4096)
+            if (rb == 7 && tile == 4096)
+                launch("onesweep_records_packed_t4096_d7", s, [&] {
+                    onesweep_kernel<uint64_t, S, 256, 16, 1, uint32_t, false, 7><<<tiles, 256, 0, s>>>(
+                        in, nullptr, out, nullptr, (uint32_t)n, shift, b, stw, tickets + pass);
+                });
+            else if (rb == 7)
+                launch("onesweep_records_packed_t8192_d7", s, [&] {
+                    onesweep_kernel<uint64_t, S, 512, 16, 1, uint32_t, false, 7><<<tiles, 512, 0, s>>>(
+                        in, nullptr, out, nullptr, (uint32_t)n, shift, b, stw, tickets + pass);
+                });
+            else if (tile == 4096)
                 launch("onesweep_records_packed_t4096", s, [&] {
                     onesweep_kernel<uint64_t, S, 256, 16, 1, uint32_t, false><<<tiles, 256, 0, s>>>(
                         in, nullptr, out, nullptr, (uint32_t)n, shift, b, stw, tickets + pass);
@@ -636,14 +683,14 @@ void reduce_hist(const uint32_t *part, int nblocks, int passes, uint32_t *counts
     });
 }
 
-// Passes whose digit is not the same for every key.
-std::vector<int> live_shifts(const uint32_t *counts, int passes, uint64_t n) {
+// Passes whose digit is not the same for every key (digits of rb bits).
+std::vector<int> live_shifts(const uint32_t *counts, int passes, uint64_t n, int rb = kRadixBits) {
     std::vector<int> sh;
     for (int p = 0; p < passes; ++p) {
         bool trivial = false;
         for (int d = 0; d < kRadix; ++d)
             if (counts[p * kRadix + d] == n) trivial = true;
-        if (!trivial) sh.push_back(p * kRadixBits);
+        if (!trivial) sh.push_back(p * rb);
     }
     return sh;
 }
@@ -667,6 +714,47 @@ void scan_launch(const char *name, const Prob &p, uint64_t n, uint64_t *status, 
 
 // ---------------------------------------------------------------------------
 // Plan construction, per-point part.
+
+// Key-length classes of the record sort at digit width rb (one instance
+// only: the instance bits of a batch sit above every node id, so nearly all
+// keys would share one class).  Classes are merged from the short end until
+// their histogram rows fit the flat map's LDS.  Returns false when the sort
+// cannot run at this width (more digit passes than the kernels hold).
+bool class_layout(Plan *P, int rb) {
+    const int cmax = std::max(1, (int)ceil_div(P->key_bits, rb));
+    if (cmax > kMaxPasses) return false;
+    P->ncls = 1;
+    P->cls_c0 = 0;
+    P->cls_rows = 0;
+    for (int q = 0; q < kMaxClasses; ++q) {
+        P->cls_passes[q] = 0;
+        P->cls_row0[q] = 0;
+        P->cls_mask[q] = 0;
+        P->cls_tot[q] = 0;
+    }
+    if (P->batched || P->nax < 1) return true;
+    const int cmin = (int)ceil_div(P->field_shift[0] + 1, rb);
+    const int cap = P->key64 ? 26 : 10;
+    int nc = std::min(kMaxClasses, cmax - cmin + 1);
+    while (nc >= 2 && nc * cmax - nc * (nc - 1) / 2 > cap) --nc;
+    if (nc < 2) return true;
+    P->ncls = nc;
+    P->cls_c0 = cmax - nc + 1;
+    int row = 0;
+    for (int q = 0; q < nc; ++q) {
+        P->cls_passes[q] = P->cls_c0 + q;
+        P->cls_row0[q] = row;
+        row += P->cls_passes[q];
+    }
+    P->cls_rows = row;
+    const int L0 = P->Lmax[0];
+    for (int j = 0; j < L0; ++j) {
+        const int nominal = (int)ceil_div(P->field_shift[0] + j + 1, rb);
+        const int q = std::max(nominal, P->cls_c0) - P->cls_c0;
+        P->cls_mask[q] |= 1u << (L0 - 1 - j);
+    }
+    return true;
+}
 
 template <class C, class KP>
 void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const int64_t *qoff,
@@ -831,8 +919,10 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
     const bool pack_ok = packing_enabled();
     P->pay_bits = 1 + bits_for((uint64_t)std::max<int64_t>(std::max(P->nD, P->nQ), 1));
     if (P->inline_req && nax > 0) {
-        // the query flag goes one bit above the digits the record sort reads
-        const int fs = kRadixBits * std::max(1, (int)ceil_div(P->key_bits, kRadixBits));
+        // the query flag goes one bit above the digits the record sort reads,
+        // at either digit width
+        int fs = 0;
+        for (int rb : {7, 8}) fs = std::max(fs, rb * std::max(1, (int)ceil_div(P->key_bits, rb)));
         const bool packs = pack_ok && fs + 1 + 32 <= 64;
         if (fs < 64 && (packs || !pack_ok)) {
             P->inline_w = true;
@@ -873,30 +963,7 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
         sig_vals64 = std::move(inB ? wB : wA);
         pr.reset();
     }
-    // Key-length classes (one instance only: the instance bits of a batch sit
-    // above every node id, so nearly all keys would share one class).
-    if (!P->batched && nax >= 1) {
-        const int cmax = (int)ceil_div(P->key_bits, kRadixBits);
-        const int cmin = (int)ceil_div(P->field_shift[0] + 1, kRadixBits);
-        const int nc = std::min(kMaxClasses, cmax - cmin + 1);
-        if (nc >= 2) {
-            P->ncls = nc;
-            P->cls_c0 = cmax - nc + 1;
-            int row = 0;
-            for (int q = 0; q < nc; ++q) {
-                P->cls_passes[q] = P->cls_c0 + q;
-                P->cls_row0[q] = row;
-                row += P->cls_passes[q];
-            }
-            P->cls_rows = row;
-            const int L0 = P->Lmax[0];
-            for (int j = 0; j < L0; ++j) {
-                const int nominal = (int)ceil_div(P->field_shift[0] + j + 1, kRadixBits);
-                const int q = std::max(nominal, P->cls_c0) - P->cls_c0;
-                P->cls_mask[q] |= 1u << (L0 - 1 - j);
-            }
-        }
-    }
+    class_layout(P, P->rbits);
     {
         uint64_t S = 1;
         for (int a = 0; a < nax; ++a) S *= (uint64_t)std::max(P->Lmax[a], 1);
@@ -990,7 +1057,7 @@ uint32_t skewed_passes(const Plan *P) {
     uint32_t skew = 0;
     auto mark = [&](int lo, int hi) {  // bits [lo, hi)
         for (int p = 0; p < kMaxPasses; ++p)
-            if (p * kRadixBits < hi && (p + 1) * kRadixBits > lo) skew |= 1u << p;
+            if (p * P->rbits < hi && (p + 1) * P->rbits > lo) skew |= 1u << p;
     };
     for (int a = 0; a < P->nax; ++a) {
         const int top = P->field_shift[a] + P->Lmax[a];  // one past the field's top bit
@@ -1023,7 +1090,8 @@ void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &ou
             vB.alloc(E * 4, s);
         }
     }
-    const int passes = cls ? P->cls_passes[P->ncls - 1] : std::max(1, (int)ceil_div(P->key_bits, kRadixBits));
+    const int rb = P->rbits;
+    const int passes = cls ? P->cls_passes[P->ncls - 1] : std::max(1, (int)ceil_div(P->key_bits, rb));
     const int rows = cls ? P->cls_rows : passes;
     if (rows > (sizeof(K) == 4 ? 10 : 26) || passes > kMaxPasses)
         fail(DOM_AGG_EHIP, "internal: %d histogram rows for %d-byte keys", rows, (int)sizeof(K));
@@ -1098,6 +1166,7 @@ void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &ou
     a.ncls = P->ncls;
     a.cls_c0 = P->cls_c0;
     a.hist_rows = rows;
+    a.rbits = rb;
     for (int q = 0; q < kMaxClasses; ++q) {
         a.cls_passes[q] = P->cls_passes[q];
         a.cls_row0[q] = P->cls_row0[q];
@@ -1202,6 +1271,7 @@ void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &ou
         h.passes = passes;
         h.pay_bits = P->pay_bits;
         h.rows = rows;
+        h.rbits = rb;
         h.skew = skewed_passes(P);
         const unsigned hgrid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(ceil_div(E, kBlock * 4), 1024));
         DevBuf hpart;
@@ -1225,9 +1295,9 @@ void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &ou
         if (h[rows * kRadix + 2]) fail(DOM_AGG_EHIP, "internal: flat-map records disagree with their class counts");
         if (cls) {
             P->rec_shifts.clear();
-            for (int p = 0; p < passes; ++p) P->rec_shifts.push_back(p * kRadixBits);
+            for (int p = 0; p < passes; ++p) P->rec_shifts.push_back(p * rb);
         } else {
-            P->rec_shifts = P->key_bits ? live_shifts(h, passes, E) : std::vector<int>{};
+            P->rec_shifts = P->key_bits ? live_shifts(h, passes, E, rb) : std::vector<int>{};
         }
         uint64_t ed;
         std::memcpy(&ed, h + rows * kRadix, 8);
@@ -1240,19 +1310,19 @@ void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &ou
             if (nq == 0) continue;
             const int np = P->cls_passes[q];
             std::vector<int> shifts;
-            for (int p = 0; p < np; ++p) shifts.push_back(p * kRadixBits);
+            for (int p = 0; p < np; ++p) shifts.push_back(p * rb);
             const uint64_t b = a.cls_base[q];
             const uint32_t *cb = bases.as<uint32_t>() + (size_t)P->cls_row0[q] * kRadix;
             if (pk) {
                 uint64_t *pa = kA.as<uint64_t>() + b, *pb = kB.as<uint64_t>() + b;
-                if (np & 1) radix_sort_packed(pa, pb, nq, shifts, P->pay_bits, cb, P->tune.record_sort_tile, s);
-                else radix_sort_packed(pb, pa, nq, shifts, P->pay_bits, cb, P->tune.record_sort_tile, s);
+                if (np & 1) radix_sort_packed(pa, pb, nq, shifts, P->pay_bits, cb, P->tune.record_sort_tile, s, rb);
+                else radix_sort_packed(pb, pa, nq, shifts, P->pay_bits, cb, P->tune.record_sort_tile, s, rb);
             } else if (np & 1)
                 radix_sort<K, 1>(kA.as<K>() + b, vA.as<uint32_t>() + b, kB.as<K>() + b, vB.as<uint32_t>() + b, nq,
-                                 shifts, cb, P->tune.record_sort_tile, s);
+                                 shifts, cb, P->tune.record_sort_tile, s, rb);
             else
                 radix_sort<K, 1>(kB.as<K>() + b, vB.as<uint32_t>() + b, kA.as<K>() + b, vA.as<uint32_t>() + b, nq,
-                                 shifts, cb, P->tune.record_sort_tile, s);
+                                 shifts, cb, P->tune.record_sort_tile, s, rb);
         }
         outK = std::move(kB);
         outV = std::move(vB);
@@ -1263,12 +1333,12 @@ void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &ou
         if (pk) {
             kB.alloc(E * 8, s);
             inB = radix_sort_packed(kA.as<uint64_t>(), kB.as<uint64_t>(), E, P->rec_shifts, P->pay_bits,
-                                    bases.as<uint32_t>(), P->tune.record_sort_tile, s);
+                                    bases.as<uint32_t>(), P->tune.record_sort_tile, s, rb);
         } else {
             kB.alloc(E * sizeof(K), s);
             vB.alloc(E * 4, s);
             inB = radix_sort<K, 1>(kA.as<K>(), vA.as<uint32_t>(), kB.as<K>(), vB.as<uint32_t>(), E, P->rec_shifts,
-                                bases.as<uint32_t>(), P->tune.record_sort_tile, s);
+                                bases.as<uint32_t>(), P->tune.record_sort_tile, s, rb);
         }
     }
     outK = std::move(inB ? kB : kA);
@@ -1644,10 +1714,13 @@ void maybe_graph(Plan *P, const std::vector<uintptr_t> &key, hipStream_t s, F &&
 
 
 // ---------------------------------------------------------------------------
-// Autotuner: times the record sort (flat map + radix passes) and the forward
-// scan for each tile candidate on the plan's own records and keeps the
-// fastest.  Results are cached per (m, key bits, ceil(log2 E)).  The sorted
-// records do not depend on the tile, so the plan's records are kept as built.
+// Autotuner: times the record sort (flat map + radix passes) for each digit
+// width and tile candidate, and the forward scan for each tile, on the plan's
+// own records and keeps the fastest.  Results are cached per (device, record
+// kind, key bits, ceil(log2 E)).  The sorted records depend on neither the
+// digit width nor the tile, so the plan's records are kept as built; the
+// per-width state (key-length classes, their totals, the live passes) is
+// probed again for the width kept.
 
 float time_ms(hipStream_t s, const std::function<void()> &f) {
     hipEvent_t a, b;
@@ -1664,9 +1737,38 @@ float time_ms(hipStream_t s, const std::function<void()> &f) {
     return ms;
 }
 
-// (records carrying weights are tuned separately: their keys may be wider)
+// The cache's device name: architecture and compute-unit count.
+std::string device_signature() {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    static std::mutex mu;
+    static std::map<int, std::string> sig;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = sig.find(dev);
+    if (it == sig.end()) {
+        hipDeviceProp_t prop;
+        HIPCHK(hipGetDeviceProperties(&prop, dev));
+        it = sig.emplace(dev, std::string(prop.gcnArchName) + "/" + std::to_string(prop.multiProcessorCount)).first;
+    }
+    return it->second;
+}
+
+// (records carrying weights, packed records and the basic variant are tuned
+// separately: their keys and record widths differ; so are plans whose digit
+// width DOM_AGG_DIGIT_BITS fixes)
 TuneKey tune_key(const Plan *P) {
-    return TuneKey{P->m + (P->inline_w ? 16 : 0), P->key_bits, bits_for((uint64_t)P->E)};
+    const int kind = P->m | (P->inline_w ? 16 : 0) | (P->packed ? 32 : 0) | (P->basic ? 64 : 0) |
+                     (forced_digit_bits() << 8);
+    return TuneKey{device_signature(), kind, P->key_bits, bits_for((uint64_t)P->E)};
+}
+
+// Builds the plan's records with the probe (class totals, live passes) and
+// drops them.
+void probe_records(Plan *P, hipStream_t s) {
+    HostStage hs;
+    DevBuf k, v;
+    if (P->key64) build_records<uint64_t>(P, s, &hs, true, k, v);
+    else build_records<uint32_t>(P, s, &hs, true, k, v);
 }
 
 // Applies a cached choice; called before the records are built, so that the
@@ -1676,8 +1778,13 @@ bool tune_lookup(Plan *P) {
     if (!tc.enabled() || P->E <= 0) return false;
     TuneChoice c;
     if (!tc.lookup(tune_key(P), &c)) return false;
+    if (c.digit_bits != P->rbits) {
+        if (!class_layout(P, c.digit_bits)) return false;
+        P->rbits = c.digit_bits;
+    }
     P->tune.record_sort_tile = c.record_sort_tile;
     P->tune.scan_items = c.scan_items;
+    P->tune.digit_bits = c.digit_bits;
     return true;
 }
 
@@ -1688,22 +1795,41 @@ void tune_plan(Plan *P, hipStream_t s) {
     const TuneKey key = tune_key(P);
     // the per-point state is still present here (plan construction)
     float best = 1e30f;
-    int best_tile = P->tune.record_sort_tile;
-    for (int tile : {2048, 4096, 8192, 16384}) {
-        if (effective_tile<uint32_t, 1>(tile) != tile || (P->key64 && tile == 16384)) continue;
-        if (P->packed && tile != 4096 && tile != 8192) continue;  // (the packed sort's two tile shapes)
-        P->tune.record_sort_tile = tile;
-        DevBuf k, v;
-        const float ms = time_ms(s, [&] {
-            if (P->key64) build_records<uint64_t>(P, s, nullptr, false, k, v);
-            else build_records<uint32_t>(P, s, nullptr, false, k, v);
-        });
-        if (ms < best) {
-            best = ms;
-            best_tile = tile;
+    int best_tile = P->tune.record_sort_tile, best_rb = P->rbits;
+    int probed_rb = P->rbits;  // the width whose state the plan holds
+    const int fdb = forced_digit_bits();
+    for (int rb : {8, 7}) {
+        if (fdb && rb != fdb) continue;
+        if (rb != probed_rb) {
+            if (!class_layout(P, rb)) continue;
+            P->rbits = rb;
+            probe_records(P, s);  // (also the first run at this width)
+            probed_rb = rb;
+        }
+        for (int tile : {2048, 4096, 8192, 16384}) {
+            if (effective_tile<uint32_t, 1>(tile) != tile || (P->key64 && tile == 16384)) continue;
+            // (the packed sort's and the 7-bit sort's two tile shapes)
+            if ((P->packed || rb == 7) && tile != 4096 && tile != 8192) continue;
+            P->tune.record_sort_tile = tile;
+            DevBuf k, v;
+            const float ms = time_ms(s, [&] {
+                if (P->key64) build_records<uint64_t>(P, s, nullptr, false, k, v);
+                else build_records<uint32_t>(P, s, nullptr, false, k, v);
+            });
+            if (ms < best) {
+                best = ms;
+                best_tile = tile;
+                best_rb = rb;
+            }
         }
     }
+    if (best_rb != probed_rb) {
+        if (!class_layout(P, best_rb)) fail(DOM_AGG_EHIP, "internal: digit width %d lost its layout", best_rb);
+        P->rbits = best_rb;
+        probe_records(P, s);
+    }
     P->tune.record_sort_tile = best_tile;
+    P->tune.digit_bits = best_rb;
     if (!P->key64 && P->rkeys.p && P->nQ > 0) {
         ensure_part(P, 8, s);
         DevBuf out;
@@ -1854,6 +1980,14 @@ std::unique_ptr<Plan> make_plan(int m, dom_agg_dtype coord_dtype, const void *d_
         P->scan_ticket.alloc(16, s);
         if (P->E > 0) {
             const bool tuned = !(flags & DOM_AGG_NO_TUNE) && tune_lookup(P.get());
+            if (const int fdb = forced_digit_bits()) {
+                if (fdb != P->rbits) {
+                    if (!class_layout(P.get(), fdb))
+                        fail(DOM_AGG_EINVAL, "the record key (%d bits) needs more than %d passes of %d-bit digits",
+                             P->key_bits, kMaxPasses, fdb);
+                    P->rbits = fdb;
+                }
+            }
             DevBuf k, v;
             if (P->key64) build_records<uint64_t>(P.get(), s, &hs, true, k, v);
             else build_records<uint32_t>(P.get(), s, &hs, true, k, v);
@@ -2076,7 +2210,7 @@ dom_agg_status dom_agg_plan_get_info(dom_agg_plan_t plan, dom_agg_plan_info *inf
         info->key_bits = plan->key_bits;
         for (int a = 0; a < 3; ++a) info->L[a] = plan->Lmax[a];  // (nax <= 3 axes)
         info->sort_passes = (int32_t)plan->rec_shifts.size();
-        info->digit_bits = kRadixBits;
+        info->digit_bits = plan->rbits;
         info->sort_tile = plan->tune.record_sort_tile;
         info->scan_tile = kBlock * ((plan->tune.scan_items == 8 || plan->key64) ? 8 : 16);
         info->regroup_slots = plan->use_slots ? (int32_t)plan->n_slots : 0;

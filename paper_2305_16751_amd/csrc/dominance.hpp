@@ -518,6 +518,7 @@ struct EmitArgs {
     int cls_passes[kMaxClasses];
     int cls_row0[kMaxClasses];           // first histogram row of each class
     int hist_rows;                       // sum of cls_passes
+    int rbits;                           // digit width of the record sort (<= 8)
     uint64_t cls_base[kMaxClasses];      // region starts
     uint32_t cls_mask[kMaxClasses];      // first-axis levels of each class (bit L-1-j for level j)
     const uint32_t *cls_off;             // [chunks][kMaxClasses]: records of each class before the chunk
@@ -553,9 +554,9 @@ __device__ __forceinline__ uint32_t packed_prefix(uint64_t packed, int q) {
 }
 
 template <class K>
-__device__ __forceinline__ int key_class(K key, int c0) {
+__device__ __forceinline__ int key_class(K key, int c0, int rb) {
     const int bits = (int)(sizeof(K) * 8) - (sizeof(K) == 8 ? __clzll((long long)key) : __clz((int)key));
-    const int nominal = (bits + kRadixBits - 1) / kRadixBits;
+    const int nominal = (bits + rb - 1) / rb;
     return (nominal > c0 ? nominal : c0) - c0;
 }
 
@@ -725,7 +726,7 @@ __global__ __launch_bounds__(256) void node_hist_kernel(const uint32_t *__restri
         const uint64_t lo = P << (L - j);
         const uint32_t cnt = (cd(lo + half) - cd(lo)) + (cq(lo + 2 * half) - cq(lo + half));
         if (cnt == 0) continue;
-        const int q = key_class((uint32_t)t, a.cls_c0);
+        const int q = key_class((uint32_t)t, a.cls_c0, a.rbits);
         int row0 = 0;
 #pragma unroll
         for (int c = 0; c < kMaxClasses; ++c)
@@ -734,8 +735,9 @@ __global__ __launch_bounds__(256) void node_hist_kernel(const uint32_t *__restri
 #pragma unroll
         for (int c = 1; c < kMaxClasses; ++c)
             if (c == q) np = a.cls_passes[c];
+        const uint32_t dmask = (1u << a.rbits) - 1u;
         for (int p = 0; p < np; ++p)
-            atomicAdd(&s_hist[(row0 + p) * kRadix + ((uint32_t)(t >> (kRadixBits * p)) & (kRadix - 1))], cnt);
+            atomicAdd(&s_hist[(row0 + p) * kRadix + ((uint32_t)(t >> (a.rbits * p)) & dmask)], cnt);
     }
     __syncthreads();
     if (rows) hist_flush(s_hist, a.hist_part, rows);
@@ -768,14 +770,16 @@ __global__ __launch_bounds__(256) void node_hist_kernel(const uint32_t *__restri
 // lanes sharing the first active lane's row and digit are added with one
 // atomic.  All lanes of the wavefront call it, for max_np passes.
 template <class K>
-__device__ __forceinline__ void hist_add_rows(uint32_t *s_hist, K key, bool valid, int row0, int np, int max_np) {
+__device__ __forceinline__ void hist_add_rows(uint32_t *s_hist, K key, bool valid, int row0, int np, int max_np,
+                                              int rb) {
     const int lane = lane_id();
+    const uint32_t dmask = (1u << rb) - 1u;
     for (int p = 0; p < max_np; ++p) {
         const bool v = valid && p < np;
         const uint64_t act = __ballot(v);
         if (act == 0) continue;
         const int leader = __ffsll((unsigned long long)act) - 1;
-        const uint32_t idx = (uint32_t)(row0 + p) * kRadix + ((uint32_t)(key >> (kRadixBits * p)) & (kRadix - 1));
+        const uint32_t idx = (uint32_t)(row0 + p) * kRadix + ((uint32_t)(key >> (rb * p)) & dmask);
         const uint32_t i0 = read_lane_u32(idx, leader);
         const uint64_t same = __ballot(v && idx == i0);
         if (lane == leader) atomicAdd(&s_hist[i0], (uint32_t)__popcll(same));
@@ -800,6 +804,7 @@ struct RecHistArgs {
     int passes;             // without classes; with classes the largest class's
     int pay_bits;
     int rows;
+    int rbits;              // digit width (<= 8)
     uint32_t skew;          // bit p: pass p's digit is skewed (holds a field's top bits)
     uint32_t *hist_part;    // [gridDim.x][rows][256]
 };
@@ -809,11 +814,12 @@ struct RecHistArgs {
 // atomic per lane.
 template <class K>
 __device__ __forceinline__ void hist_add_rows_skew(uint32_t *s_hist, K key, bool valid, int row0, int np,
-                                                   int max_np, uint32_t skew) {
+                                                   int max_np, uint32_t skew, int rb) {
     const int lane = lane_id();
+    const uint32_t dmask = (1u << rb) - 1u;
     for (int p = 0; p < max_np; ++p) {
         const bool v = valid && p < np;
-        const uint32_t idx = (uint32_t)(row0 + p) * kRadix + ((uint32_t)(key >> (kRadixBits * p)) & (kRadix - 1));
+        const uint32_t idx = (uint32_t)(row0 + p) * kRadix + ((uint32_t)(key >> (rb * p)) & dmask);
         if (!((skew >> p) & 1u)) {
             if (v) atomicAdd(&s_hist[idx], 1u);
             continue;
@@ -861,7 +867,7 @@ __global__ __launch_bounds__(256) void record_hist_kernel(RecHistArgs a) {
             const int c = q[u];
             const int row0 = a.ncls > 1 ? a.cls_row0[c] : 0;
             const int np = a.ncls > 1 ? a.cls_passes[c] : a.passes;
-            hist_add_rows_skew(s_hist, key[u], valid, row0, np, a.passes, a.skew);
+            hist_add_rows_skew(s_hist, key[u], valid, row0, np, a.passes, a.skew, a.rbits);
         }
     }
     __syncthreads();
@@ -1297,7 +1303,7 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(EmitArgs a, K *__restrict__
                     key = pw.template key<K>(a.inst_shift, with_inst, a.field_shift, a.flag_shift);
                     uint32_t lp = threadIdx.x * ITEMS + j;
                     if constexpr (CLS) {
-                        const int q = key_class(key & kmask, a.cls_c0);
+                        const int q = key_class(key & kmask, a.cls_c0, a.rbits);
                         lp = packed_prefix(tot, q) + ((uint32_t)(mine >> (16 * q)) & 0xffffu);
                         mine += 1ull << (16 * q);
                         seen += 1ull << (16 * q);
@@ -1319,11 +1325,13 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(EmitArgs a, K *__restrict__
                     }
                 }
                 if constexpr (!CLS) {
-                    if (rows) hist_add(s_hist, key, valid, a.passes, peel_from);
+                    if (rows) hist_add(s_hist, key & kmask, valid, a.passes, peel_from, a.rbits);
                 } else {
-                    const int q = valid ? key_class(key & kmask, a.cls_c0) : 0;
+                    const int q = valid ? key_class(key & kmask, a.cls_c0, a.rbits) : 0;
                     const uint32_t ci = (uint32_t)(cls_info >> (16 * q));
-                    if (rows) hist_add_rows(s_hist, key, valid, (int)(ci & 0xffu), (int)((ci >> 8) & 0xffu), a.passes);
+                    if (rows)
+                        hist_add_rows(s_hist, key & kmask, valid, (int)(ci & 0xffu), (int)((ci >> 8) & 0xffu),
+                                      a.passes, a.rbits);
                 }
             }
             if constexpr (CLS) {

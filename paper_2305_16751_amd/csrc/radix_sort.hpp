@@ -27,15 +27,17 @@ constexpr int kMaxPasses = 8;  // 64-bit keys
 // peel_from on, lanes sharing the first valid lane's digit are added with
 // one atomic (skewed digits, such as the high digits of the tree-node keys,
 // would otherwise serialise on one LDS address).
+// rb: the digit width (<= 8; rows stay 256 bins wide).
 template <class K>
 __device__ __forceinline__ void hist_add(uint32_t *s_hist, K key, bool valid, int passes,
-                                         int peel_from = 0) {
+                                         int peel_from = 0, int rb = kRadixBits) {
     const uint64_t act = __ballot(valid);
     if (act == 0) return;
     const int leader = __ffsll((unsigned long long)act) - 1;
     const int lane = lane_id();
+    const uint32_t dmask = (1u << rb) - 1u;
     for (int p = 0; p < passes; ++p) {
-        const uint32_t d = (uint32_t)(key >> (kRadixBits * p)) & (kRadix - 1);
+        const uint32_t d = (uint32_t)(key >> (rb * p)) & dmask;
         if (p < peel_from) {  // digits known to be spread: one LDS atomic per lane
             if (valid) atomicAdd(&s_hist[p * kRadix + d], 1u);
             continue;
