@@ -374,6 +374,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="only the headline workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 20)
+    ap.add_argument("--workload", choices=("f32_2d_16m", "f32_3d_1m"), default="f32_2d_16m",
+                    help="the one-shot workload of the JSON line (profiling the m = 3 case; the metric's "
+                         "workload is f32_2d_16m)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB elementwise copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -393,7 +396,7 @@ def main():
         torch.add(a, 0.0, out=b)  # reads 1 GiB, writes 1 GiB
         torch.cuda.synchronize()
         del a, b
-    case = workloads.f32_2d_16m()
+    case = getattr(workloads, args.workload)()
     log(f"headline: {case.name} m={case.m} |D|={case.D.shape[0]} |Q|={case.Q.shape[0]}")
     T, kern, info, _ = run_oneshot(case, args.steps, args.warmup)
     value = case.n * args.steps / T

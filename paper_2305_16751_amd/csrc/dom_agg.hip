@@ -267,6 +267,13 @@ int forced_digit_bits() {
     return v;
 }
 
+// DOM_AGG_COMPACT=1 regroups through the compact per-row layout even where
+// the level-tuple slot table would be used (for measurement and tests).
+bool compact_forced() {
+    const char *e = std::getenv("DOM_AGG_COMPACT");
+    return e && e[0] == '1';
+}
+
 // DOM_AGG_PACK=0 keeps records as separate key and payload arrays (for
 // measurement); packing is on otherwise.
 // Whether the record sort's digit histograms come from a streaming pass over
@@ -361,6 +368,11 @@ struct dom_agg_plan_s {
     bool key64 = false;
     int field_shift[3] = {0, 0, 0};
     int inst_shift = 0;
+    // bits at the bottom of the record key that the sort does not read: the
+    // instance id in batches (Sec. 5 variant), whose records are emitted in
+    // instance order, so a stable sort by the node fields alone keeps each
+    // (tuple, instance) run together; 0 otherwise
+    int sort_lo = 0;
     int64_t E = 0, E_D = 0;
     std::vector<int> rec_shifts;  // radix passes the record sort runs (without classes)
     int rbits = kRadixBits;       // the record sort's digit width (7 or 8; chosen by the tuner)
@@ -563,11 +575,11 @@ void onesweep_dispatch(int tile, const K *kin, const VT *vin, K *kout, VT *vout,
 }
 
 // Sorts (kA, vA) by the listed digit shifts; returns true when the result
-// ended up in (kB, vB).  bases: [passes][256] (pass p at shift rb * p).
+// ended up in (kB, vB).  bases: [passes][256] (pass p at shift lo + rb * p).
 // rb: digit width, 8, or 7 for the record sort (tiles 4096 and 8192).
 template <class K, int ROLE, class VT = uint32_t>
 bool radix_sort(K *kA, VT *vA, K *kB, VT *vB, uint64_t n, const std::vector<int> &shifts,
-                const uint32_t *bases, int tile, hipStream_t s, int rb = kRadixBits) {
+                const uint32_t *bases, int tile, hipStream_t s, int rb = kRadixBits, int lo = 0) {
     if (n == 0 || shifts.empty()) return false;
     if (rb != kRadixBits && (ROLE != 1 || sizeof(VT) != 4 || rb != 7))
         fail(DOM_AGG_EHIP, "internal: %d-bit digits are for the record sort only", rb);
@@ -590,7 +602,7 @@ bool radix_sort(K *kA, VT *vA, K *kB, VT *vB, uint64_t n, const std::vector<int>
         const VT *vi = inB ? vB : vA;
         K *ko = inB ? kA : kB;
         VT *vo = inB ? vA : vB;
-        const uint32_t *b = bases + (sh / rb) * kRadix;
+        const uint32_t *b = bases + ((sh - lo) / rb) * kRadix;
         void *st = status.as<uint64_t>() + pass * pass_words;
         auto go = [&](auto s_c) {
             using S = decltype(s_c);
@@ -616,7 +628,7 @@ bool radix_sort(K *kA, VT *vA, K *kB, VT *vB, uint64_t n, const std::vector<int>
 // listed key digit shifts (digits of rb = 7 or 8 bits); returns true when
 // the result ended up in B.
 bool radix_sort_packed(uint64_t *A, uint64_t *B, uint64_t n, const std::vector<int> &shifts, int pay_bits,
-                       const uint32_t *bases, int tile, hipStream_t s, int rb = kRadixBits) {
+                       const uint32_t *bases, int tile, hipStream_t s, int rb = kRadixBits, int lo = 0) {
     if (rb != 7 && rb != 8) fail(DOM_AGG_EHIP, "internal: %d-bit digits", rb);
     if (n == 0 || shifts.empty()) return false;
     tile = tile == 4096 ? 4096 : 8192;
@@ -632,7 +644,7 @@ bool radix_sort_packed(uint64_t *A, uint64_t *B, uint64_t n, const std::vector<i
     for (int sh : shifts) {
         const uint64_t *in = inB ? B : A;
         uint64_t *out = inB ? A : B;
-        const uint32_t *b = bases + (sh / rb) * kRadix;
+        const uint32_t *b = bases + ((sh - lo) / rb) * kRadix;
         void *st = status.as<uint64_t>() + pass * pass_words;
         const unsigned tiles = (unsigned)ceil_div(n, (uint64_t)tile);
         const int shift = pay_bits + sh;
@@ -683,14 +695,15 @@ void reduce_hist(const uint32_t *part, int nblocks, int passes, uint32_t *counts
     });
 }
 
-// Passes whose digit is not the same for every key (digits of rb bits).
-std::vector<int> live_shifts(const uint32_t *counts, int passes, uint64_t n, int rb = kRadixBits) {
+// Passes whose digit is not the same for every key (digits of rb bits from
+// bit lo up).
+std::vector<int> live_shifts(const uint32_t *counts, int passes, uint64_t n, int rb = kRadixBits, int lo = 0) {
     std::vector<int> sh;
     for (int p = 0; p < passes; ++p) {
         bool trivial = false;
         for (int d = 0; d < kRadix; ++d)
             if (counts[p * kRadix + d] == n) trivial = true;
-        if (!trivial) sh.push_back(p * rb);
+        if (!trivial) sh.push_back(lo + p * rb);
     }
     return sh;
 }
@@ -715,13 +728,15 @@ void scan_launch(const char *name, const Prob &p, uint64_t n, uint64_t *status, 
 // ---------------------------------------------------------------------------
 // Plan construction, per-point part.
 
-// Key-length classes of the record sort at digit width rb (one instance
-// only: the instance bits of a batch sit above every node id, so nearly all
-// keys would share one class).  Classes are merged from the short end until
-// their histogram rows fit the flat map's LDS.  Returns false when the sort
-// cannot run at this width (more digit passes than the kernels hold).
+// Key-length classes of the record sort at digit width rb, over the key bits
+// the sort reads (from sort_lo up; not for a basic-variant batch, whose
+// instance bits sit above every node id, so nearly all keys would share one
+// class).  Classes are merged from the short end until their histogram rows
+// fit the flat map's LDS.  Returns false when the sort cannot run at this
+// width (more digit passes than the kernels hold).
 bool class_layout(Plan *P, int rb) {
-    const int cmax = std::max(1, (int)ceil_div(P->key_bits, rb));
+    const int lo = P->sort_lo;
+    const int cmax = std::max(1, (int)ceil_div(P->key_bits - lo, rb));
     if (cmax > kMaxPasses) return false;
     P->ncls = 1;
     P->cls_c0 = 0;
@@ -732,8 +747,8 @@ bool class_layout(Plan *P, int rb) {
         P->cls_mask[q] = 0;
         P->cls_tot[q] = 0;
     }
-    if (P->batched || P->nax < 1) return true;
-    const int cmin = (int)ceil_div(P->field_shift[0] + 1, rb);
+    if ((P->batched && lo == 0) || P->nax < 1) return true;
+    const int cmin = (int)ceil_div(P->field_shift[0] + 1 - lo, rb);
     const int cap = P->key64 ? 26 : 10;
     int nc = std::min(kMaxClasses, cmax - cmin + 1);
     while (nc >= 2 && nc * cmax - nc * (nc - 1) / 2 > cap) --nc;
@@ -749,7 +764,7 @@ bool class_layout(Plan *P, int rb) {
     P->cls_rows = row;
     const int L0 = P->Lmax[0];
     for (int j = 0; j < L0; ++j) {
-        const int nominal = (int)ceil_div(P->field_shift[0] + j + 1, rb);
+        const int nominal = (int)ceil_div(P->field_shift[0] + j + 1 - lo, rb);
         const int q = std::max(nominal, P->cls_c0) - P->cls_c0;
         P->cls_mask[q] |= 1u << (L0 - 1 - j);
     }
@@ -902,13 +917,19 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
             P->Lmax[a] = lm;
         }
     }
-    int sum = 0;
+    // Key layout: node fields of the expanded axes (first axis highest).  In
+    // a batch the instance id sits below them (not sorted on, see sort_lo),
+    // except in the basic variant, whose points are not in instance order
+    // (data of every instance first): there it sits above them.
+    const bool inst_low = P->batched && !P->basic;
+    P->sort_lo = inst_low ? P->inst_bits : 0;
+    int sum = P->sort_lo;
     for (int a = nax - 1; a >= 0; --a) {
         P->field_shift[a] = sum;
         sum += P->Lmax[a];
     }
-    P->inst_shift = P->batched ? sum : 0;
-    P->key_bits = sum + (P->batched ? P->inst_bits : 0);
+    P->inst_shift = P->batched && !inst_low ? sum : 0;
+    P->key_bits = sum + (P->batched && !inst_low ? P->inst_bits : 0);
     if (P->key_bits > 64) fail(DOM_AGG_ETOOBIG, "record sort key needs %d bits (> 64)", P->key_bits);
     P->key64 = P->key_bits > 32;
     // Records as single 64-bit words when key and payload fit: 32 weight
@@ -922,7 +943,8 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
         // the query flag goes one bit above the digits the record sort reads,
         // at either digit width
         int fs = 0;
-        for (int rb : {7, 8}) fs = std::max(fs, rb * std::max(1, (int)ceil_div(P->key_bits, rb)));
+        for (int rb : {7, 8})
+            fs = std::max(fs, P->sort_lo + rb * std::max(1, (int)ceil_div(P->key_bits - P->sort_lo, rb)));
         const bool packs = pack_ok && fs + 1 + 32 <= 64;
         if (fs < 64 && (packs || !pack_ok)) {
             P->inline_w = true;
@@ -968,7 +990,7 @@ void build_points(Plan *P, const C *dq, const C *qq, const int64_t *doff, const 
         uint64_t S = 1;
         for (int a = 0; a < nax; ++a) S *= (uint64_t)std::max(P->Lmax[a], 1);
         const uint64_t rows = (uint64_t)std::max(P->nQ, P->nD);
-        P->use_slots = S <= kMaxSlots && S * rows * 8 <= kMaxSlotBytes;
+        P->use_slots = nax == 0 || (S <= kMaxSlots && S * rows * 8 <= kMaxSlotBytes && !compact_forced());
         P->n_slots = (uint32_t)std::min<uint64_t>(S, 0xffffffffu);
     }
 
@@ -1057,13 +1079,13 @@ uint32_t skewed_passes(const Plan *P) {
     uint32_t skew = 0;
     auto mark = [&](int lo, int hi) {  // bits [lo, hi)
         for (int p = 0; p < kMaxPasses; ++p)
-            if (p * P->rbits < hi && (p + 1) * P->rbits > lo) skew |= 1u << p;
+            if (P->sort_lo + p * P->rbits < hi && P->sort_lo + (p + 1) * P->rbits > lo) skew |= 1u << p;
     };
     for (int a = 0; a < P->nax; ++a) {
         const int top = P->field_shift[a] + P->Lmax[a];  // one past the field's top bit
         if (P->Lmax[a] > 0) mark(top - 1, top);
     }
-    if (P->batched) mark(P->inst_shift, P->inst_shift + P->inst_bits);
+    if (P->batched && P->sort_lo == 0) mark(P->inst_shift, P->inst_shift + P->inst_bits);
     return skew;
 }
 
@@ -1090,8 +1112,8 @@ void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &ou
             vB.alloc(E * 4, s);
         }
     }
-    const int rb = P->rbits;
-    const int passes = cls ? P->cls_passes[P->ncls - 1] : std::max(1, (int)ceil_div(P->key_bits, rb));
+    const int rb = P->rbits, lo = P->sort_lo;
+    const int passes = cls ? P->cls_passes[P->ncls - 1] : std::max(1, (int)ceil_div(P->key_bits - lo, rb));
     const int rows = cls ? P->cls_rows : passes;
     if (rows > (sizeof(K) == 4 ? 10 : 26) || passes > kMaxPasses)
         fail(DOM_AGG_EHIP, "internal: %d histogram rows for %d-byte keys", rows, (int)sizeof(K));
@@ -1167,6 +1189,9 @@ void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &ou
     a.cls_c0 = P->cls_c0;
     a.hist_rows = rows;
     a.rbits = rb;
+    a.sort_lo = lo;
+    a.skew = skewed_passes(P);
+    a.lmax0 = P->nax > 0 ? P->Lmax[0] : 0;
     for (int q = 0; q < kMaxClasses; ++q) {
         a.cls_passes[q] = P->cls_passes[q];
         a.cls_row0[q] = P->cls_row0[q];
@@ -1272,6 +1297,7 @@ void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &ou
         h.pay_bits = P->pay_bits;
         h.rows = rows;
         h.rbits = rb;
+        h.sort_lo = lo;
         h.skew = skewed_passes(P);
         const unsigned hgrid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(ceil_div(E, kBlock * 4), 1024));
         DevBuf hpart;
@@ -1295,9 +1321,9 @@ void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &ou
         if (h[rows * kRadix + 2]) fail(DOM_AGG_EHIP, "internal: flat-map records disagree with their class counts");
         if (cls) {
             P->rec_shifts.clear();
-            for (int p = 0; p < passes; ++p) P->rec_shifts.push_back(p * rb);
+            for (int p = 0; p < passes; ++p) P->rec_shifts.push_back(lo + p * rb);
         } else {
-            P->rec_shifts = P->key_bits ? live_shifts(h, passes, E, rb) : std::vector<int>{};
+            P->rec_shifts = P->key_bits > lo ? live_shifts(h, passes, E, rb, lo) : std::vector<int>{};
         }
         uint64_t ed;
         std::memcpy(&ed, h + rows * kRadix, 8);
@@ -1310,19 +1336,21 @@ void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &ou
             if (nq == 0) continue;
             const int np = P->cls_passes[q];
             std::vector<int> shifts;
-            for (int p = 0; p < np; ++p) shifts.push_back(p * rb);
+            for (int p = 0; p < np; ++p) shifts.push_back(lo + p * rb);
             const uint64_t b = a.cls_base[q];
             const uint32_t *cb = bases.as<uint32_t>() + (size_t)P->cls_row0[q] * kRadix;
             if (pk) {
                 uint64_t *pa = kA.as<uint64_t>() + b, *pb = kB.as<uint64_t>() + b;
-                if (np & 1) radix_sort_packed(pa, pb, nq, shifts, P->pay_bits, cb, P->tune.record_sort_tile, s, rb);
-                else radix_sort_packed(pb, pa, nq, shifts, P->pay_bits, cb, P->tune.record_sort_tile, s, rb);
+                if (np & 1)
+                    radix_sort_packed(pa, pb, nq, shifts, P->pay_bits, cb, P->tune.record_sort_tile, s, rb, lo);
+                else
+                    radix_sort_packed(pb, pa, nq, shifts, P->pay_bits, cb, P->tune.record_sort_tile, s, rb, lo);
             } else if (np & 1)
                 radix_sort<K, 1>(kA.as<K>() + b, vA.as<uint32_t>() + b, kB.as<K>() + b, vB.as<uint32_t>() + b, nq,
-                                 shifts, cb, P->tune.record_sort_tile, s, rb);
+                                 shifts, cb, P->tune.record_sort_tile, s, rb, lo);
             else
                 radix_sort<K, 1>(kB.as<K>() + b, vB.as<uint32_t>() + b, kA.as<K>() + b, vA.as<uint32_t>() + b, nq,
-                                 shifts, cb, P->tune.record_sort_tile, s, rb);
+                                 shifts, cb, P->tune.record_sort_tile, s, rb, lo);
         }
         outK = std::move(kB);
         outV = std::move(vB);
@@ -1333,12 +1361,12 @@ void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &ou
         if (pk) {
             kB.alloc(E * 8, s);
             inB = radix_sort_packed(kA.as<uint64_t>(), kB.as<uint64_t>(), E, P->rec_shifts, P->pay_bits,
-                                    bases.as<uint32_t>(), P->tune.record_sort_tile, s, rb);
+                                    bases.as<uint32_t>(), P->tune.record_sort_tile, s, rb, lo);
         } else {
             kB.alloc(E * sizeof(K), s);
             vB.alloc(E * 4, s);
             inB = radix_sort<K, 1>(kA.as<K>(), vA.as<uint32_t>(), kB.as<K>(), vB.as<uint32_t>(), E, P->rec_shifts,
-                                bases.as<uint32_t>(), P->tune.record_sort_tile, s, rb);
+                                bases.as<uint32_t>(), P->tune.record_sort_tile, s, rb, lo);
         }
     }
     outK = std::move(inB ? kB : kA);
@@ -1758,7 +1786,7 @@ std::string device_signature() {
 // width DOM_AGG_DIGIT_BITS fixes)
 TuneKey tune_key(const Plan *P) {
     const int kind = P->m | (P->inline_w ? 16 : 0) | (P->packed ? 32 : 0) | (P->basic ? 64 : 0) |
-                     (forced_digit_bits() << 8);
+                     (P->batched ? 128 : 0) | (forced_digit_bits() << 8);
     return TuneKey{device_signature(), kind, P->key_bits, bits_for((uint64_t)P->E)};
 }
 

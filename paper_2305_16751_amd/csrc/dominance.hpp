@@ -519,6 +519,9 @@ struct EmitArgs {
     int cls_row0[kMaxClasses];           // first histogram row of each class
     int hist_rows;                       // sum of cls_passes
     int rbits;                           // digit width of the record sort (<= 8)
+    int sort_lo;                         // key bits below the sorted digits (a batch's instance id)
+    uint32_t skew;                       // bit p: digit pass p holds a node field's top bits (skewed)
+    int lmax0;                           // field width of the first expanded axis (the classes' level masks)
     uint64_t cls_base[kMaxClasses];      // region starts
     uint32_t cls_mask[kMaxClasses];      // first-axis levels of each class (bit L-1-j for level j)
     const uint32_t *cls_off;             // [chunks][kMaxClasses]: records of each class before the chunk
@@ -676,15 +679,17 @@ struct PointWalk {
 // in class q, s_q in the classes before it, R = records per first-axis level.
 template <int NAX>
 __device__ __forceinline__ uint64_t point_class_counts(const EmitArgs &a, uint32_t pay, const uint32_t *ranks,
-                                                       uint32_t ta, uint32_t tb) {
+                                                       uint32_t ins, uint32_t ta, uint32_t tb) {
     const bool isq = (pay & kQueryFlag) != 0u;
     uint32_t full0 = 0, R = 1;
 #pragma unroll
     for (int ax = 0; ax < NAX; ++ax) {
-        const uint32_t L = a.ltab[ax];
+        // (in a batch the instance's own widths; the class masks are over the
+        // first axis's field width, so its digit string is aligned to it)
+        const uint32_t L = a.inst_s ? a.ltab[(uint64_t)ax * a.n_inst + (ins < a.n_inst ? ins : 0u)] : a.ltab[ax];
         const uint32_t mask = L >= 32u ? 0xffffffffu : ((1u << L) - 1u);
         const uint32_t full = isq ? (ranks[ax] & mask) : (~ranks[ax] & mask);
-        if (ax == 0) full0 = full;
+        if (ax == 0) full0 = L <= (uint32_t)a.lmax0 ? full << ((uint32_t)a.lmax0 - L) : full;
         else R *= (uint32_t)__popc(full);
     }
     uint64_t packed = 0;
@@ -766,27 +771,6 @@ __global__ __launch_bounds__(256) void node_hist_kernel(const uint32_t *__restri
 // histograms of every pass (of every class) are accumulated on the way, or
 // come from node_hist_kernel.
 
-// Adds the digits of `key` for passes [0, np) to histogram rows row0 + p;
-// lanes sharing the first active lane's row and digit are added with one
-// atomic.  All lanes of the wavefront call it, for max_np passes.
-template <class K>
-__device__ __forceinline__ void hist_add_rows(uint32_t *s_hist, K key, bool valid, int row0, int np, int max_np,
-                                              int rb) {
-    const int lane = lane_id();
-    const uint32_t dmask = (1u << rb) - 1u;
-    for (int p = 0; p < max_np; ++p) {
-        const bool v = valid && p < np;
-        const uint64_t act = __ballot(v);
-        if (act == 0) continue;
-        const int leader = __ffsll((unsigned long long)act) - 1;
-        const uint32_t idx = (uint32_t)(row0 + p) * kRadix + ((uint32_t)(key >> (rb * p)) & dmask);
-        const uint32_t i0 = read_lane_u32(idx, leader);
-        const uint64_t same = __ballot(v && idx == i0);
-        if (lane == leader) atomicAdd(&s_hist[i0], (uint32_t)__popcll(same));
-        if (v && idx != i0) atomicAdd(&s_hist[idx], 1u);
-    }
-}
-
 // The record sort's digit histograms from the emitted records, in one
 // streaming pass (instead of inside the flat map's per-record loop): every
 // record of class q (its region of buffer A or B) adds the digits of its key
@@ -805,13 +789,16 @@ struct RecHistArgs {
     int pay_bits;
     int rows;
     int rbits;              // digit width (<= 8)
+    int sort_lo;            // key bits below the sorted digits
     uint32_t skew;          // bit p: pass p's digit is skewed (holds a field's top bits)
     uint32_t *hist_part;    // [gridDim.x][rows][256]
 };
 
-// hist_add_rows where only the passes in `skew` aggregate equal digits over
-// the wavefront first; the spread digits of the other passes take one LDS
-// atomic per lane.
+// Adds the digits of `key` for passes [0, np) to histogram rows row0 + p.
+// On the passes in `skew` (digits concentrated on few values) the lanes that
+// share the first active lane's row and digit are added with one atomic; the
+// spread digits of the other passes take one LDS atomic per lane.  All lanes
+// of the wavefront call it, for max_np passes.
 template <class K>
 __device__ __forceinline__ void hist_add_rows_skew(uint32_t *s_hist, K key, bool valid, int row0, int np,
                                                    int max_np, uint32_t skew, int rb) {
@@ -858,8 +845,8 @@ __global__ __launch_bounds__(256) void record_hist_kernel(RecHistArgs a) {
                 if (t < a.ncls && i >= a.cls_base[t]) c = t;
             q[u] = c;
             const int buf = a.ncls > 1 ? a.cls_in_b[c] : 0;
-            if constexpr (PK) key[u] = (K)(a.pk[buf][i] >> a.pay_bits);
-            else key[u] = static_cast<const K *>(a.keys[buf])[i];
+            if constexpr (PK) key[u] = (K)(a.pk[buf][i] >> (a.pay_bits + a.sort_lo));
+            else key[u] = static_cast<const K *>(a.keys[buf])[i] >> a.sort_lo;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -938,7 +925,7 @@ __global__ __launch_bounds__(256) void chunk_class_kernel(EmitArgs a, int chunk_
     const uint64_t base0 = ((uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(uint64_t)(kWave - 1))) * U;
     for (uint64_t kb = base0; kb < a.n; kb += stride) {
         uint64_t bs[U], es[U];
-        uint32_t pays[U], rks[U][NAX > 0 ? NAX : 1];
+        uint32_t pays[U], inss[U], rks[U][NAX > 0 ? NAX : 1];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint64_t k0 = kb + (uint64_t)u * kWave + lane;
@@ -946,6 +933,7 @@ __global__ __launch_bounds__(256) void chunk_class_kernel(EmitArgs a, int chunk_
             bs[u] = a.off[k];
             es[u] = a.off[k + 1];
             pays[u] = a.pay[k];
+            inss[u] = a.inst_s ? a.inst_s[k] : 0u;
 #pragma unroll
             for (int ax = 0; ax < NAX; ++ax) rks[u][ax] = a.rs[(uint64_t)ax * a.n + k];
         }
@@ -959,7 +947,7 @@ __global__ __launch_bounds__(256) void chunk_class_kernel(EmitArgs a, int chunk_
             if (has) {
                 end0 = (c0 + 1) << chunk_shift;
                 if (end0 > e) end0 = e;
-                v = point_class_counts<NAX>(a, pays[u], rks[u], 0u, (uint32_t)(end0 - b));
+                v = point_class_counts<NAX>(a, pays[u], rks[u], inss[u], 0u, (uint32_t)(end0 - b));
             }
             // sum over the lanes sharing a first chunk, one atomic per chunk
             uint64_t todo = __ballot(has);
@@ -975,8 +963,9 @@ __global__ __launch_bounds__(256) void chunk_class_kernel(EmitArgs a, int chunk_
             if (has && end0 < e) {
                 for (uint64_t lo = end0; lo < e; lo += (1ull << chunk_shift)) {
                     const uint64_t hi = (lo + (1ull << chunk_shift) < e) ? lo + (1ull << chunk_shift) : e;
-                    atomicAdd(&cnt[lo >> chunk_shift], (unsigned long long)point_class_counts<NAX>(
-                                                           a, pays[u], rks[u], (uint32_t)(lo - b), (uint32_t)(hi - b)));
+                    atomicAdd(&cnt[lo >> chunk_shift],
+                              (unsigned long long)point_class_counts<NAX>(a, pays[u], rks[u], inss[u],
+                                                                          (uint32_t)(lo - b), (uint32_t)(hi - b)));
                 }
             }
         }
@@ -1261,17 +1250,19 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(EmitArgs a, K *__restrict__
                         const uint32_t tb = (pcnt - ta < need) ? pcnt : ta + need;
                         if (tb > ta) {
                             uint32_t rk[NAX > 0 ? NAX : 1];
-                            uint32_t pay;
+                            uint32_t pay, ins = 0;
                             if (cached) {
                                 pay = s_pc.pay[k];
+                                if (with_inst) ins = s_pc.inst[k];
 #pragma unroll
                                 for (int ax = 0; ax < NAX; ++ax) rk[ax] = s_pc.rank[ax][k];
                             } else {
                                 pay = a.pay[klo + k];
+                                if (with_inst) ins = a.inst_s[klo + k];
 #pragma unroll
                                 for (int ax = 0; ax < NAX; ++ax) rk[ax] = a.rs[(uint64_t)ax * a.n + klo + k];
                             }
-                            expect += point_class_counts<NAX>(a, pay, rk, ta, tb);
+                            expect += point_class_counts<NAX>(a, pay, rk, ins, ta, tb);
                             need -= tb - ta;
                         }
                         ++k;
@@ -1303,7 +1294,7 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(EmitArgs a, K *__restrict__
                     key = pw.template key<K>(a.inst_shift, with_inst, a.field_shift, a.flag_shift);
                     uint32_t lp = threadIdx.x * ITEMS + j;
                     if constexpr (CLS) {
-                        const int q = key_class(key & kmask, a.cls_c0, a.rbits);
+                        const int q = key_class((key & kmask) >> a.sort_lo, a.cls_c0, a.rbits);
                         lp = packed_prefix(tot, q) + ((uint32_t)(mine >> (16 * q)) & 0xffffu);
                         mine += 1ull << (16 * q);
                         seen += 1ull << (16 * q);
@@ -1324,14 +1315,16 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(EmitArgs a, K *__restrict__
                         pw.load(a, &s_pc, cached, klo, idx, lsingle);
                     }
                 }
+                // (the digits the sort reads: above the instance bits of a batch)
+                const K hkey = (key & kmask) >> a.sort_lo;
                 if constexpr (!CLS) {
-                    if (rows) hist_add(s_hist, key & kmask, valid, a.passes, peel_from, a.rbits);
+                    if (rows) hist_add(s_hist, hkey, valid, a.passes, peel_from, a.rbits);
                 } else {
-                    const int q = valid ? key_class(key & kmask, a.cls_c0, a.rbits) : 0;
+                    const int q = valid ? key_class(hkey, a.cls_c0, a.rbits) : 0;
                     const uint32_t ci = (uint32_t)(cls_info >> (16 * q));
                     if (rows)
-                        hist_add_rows(s_hist, key & kmask, valid, (int)(ci & 0xffu), (int)((ci >> 8) & 0xffu),
-                                      a.passes, a.rbits);
+                        hist_add_rows_skew(s_hist, hkey, valid, (int)(ci & 0xffu), (int)((ci >> 8) & 0xffu),
+                                           a.passes, a.skew, a.rbits);
                 }
             }
             if constexpr (CLS) {
@@ -1718,26 +1711,43 @@ __global__ __launch_bounds__(256) void regroup_kernel(RegroupArgs a, const Out *
         if constexpr (NAX == 0) {
             add(part[o]);
         } else if constexpr (NAX == 1) {
-            // 8 slots per round, loaded before any is folded (row indices
-            // clamped below radix), folded in slot order as above
+            // 8 slots per round, loaded before any is folded, folded in
+            // slot order as above; only valid slots are loaded (neighbouring
+            // rows share their high rank digits, so whole lines of invalid
+            // partials are never fetched)
             constexpr uint32_t kU = 8;
             const uint32_t R = a.radix[0];
             for (uint32_t j0 = 0; j0 < R; j0 += kU) {
                 Out v[kU];
+                bool use[kU];
 #pragma unroll
                 for (uint32_t u = 0; u < kU; ++u) {
-                    const uint32_t j = (j0 + u < R) ? j0 + u : R - 1;
-                    v[u] = part[(uint64_t)j * a.nout + o];
+                    use[u] = j0 + u < R && ok(0, j0 + u);
+                    v[u] = use[u] ? part[(uint64_t)(j0 + u) * a.nout + o] : Out();
                 }
 #pragma unroll
                 for (uint32_t u = 0; u < kU; ++u)
-                    if (j0 + u < R && ok(0, j0 + u)) add(v[u]);
+                    if (use[u]) add(v[u]);
             }
         } else if constexpr (NAX == 2) {
+            // per first-axis level, the second axis's slots 8 at a time as above
+            constexpr uint32_t kU = 8;
+            const uint32_t R1 = a.radix[1];
             for (uint32_t j0 = 0; j0 < a.radix[0]; ++j0) {
-                const bool v0 = ok(0, j0);
-                for (uint32_t j1 = 0; j1 < a.radix[1]; ++j1)
-                    if (v0 && ok(1, j1)) add(part[((uint64_t)j0 * a.radix[1] + j1) * a.nout + o]);
+                if (!ok(0, j0)) continue;
+                const Out *row = part + (uint64_t)j0 * R1 * a.nout + o;
+                for (uint32_t j1 = 0; j1 < R1; j1 += kU) {
+                    Out v[kU];
+                    bool use[kU];
+#pragma unroll
+                    for (uint32_t u = 0; u < kU; ++u) {
+                        use[u] = j1 + u < R1 && ok(1, j1 + u);
+                        v[u] = use[u] ? row[(uint64_t)(j1 + u) * a.nout] : Out();
+                    }
+#pragma unroll
+                    for (uint32_t u = 0; u < kU; ++u)
+                        if (use[u]) add(v[u]);
+                }
             }
         } else {
             for (uint32_t j0 = 0; j0 < a.radix[0]; ++j0) {

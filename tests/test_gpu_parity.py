@@ -282,6 +282,34 @@ def test_compact_regroup_path_m4():
         assert np.array_equal(p.backward(to_dev(g)).cpu().numpy(), ga)
 
 
+@pytest.mark.parametrize("m", [1, 2, 3])
+def test_compact_layout_forced(m, monkeypatch):
+    """DOM_AGG_COMPACT=1 puts m <= 3 plans on the compact regroup layout
+    (one place per query record) that sparse m = 4 tables use: same results
+    on forward (sum, max, count), backward and a batch."""
+    monkeypatch.setenv("DOM_AGG_COMPACT", "1")
+    n = {1: 5000, 2: 6000, 3: 1500}[m]
+    c = workloads.small_case(1400 + m, m, n, n - 77, alphabet=None, coord="f32", weight="int64")
+    p = _plan(c)
+    assert p.info()["regroup_slots"] == (1 if m == 1 else 0), p.info()
+    check_exact(p.forward(to_dev(c.w), "sum"), oracle.construction(m, c.D, c.Q, c.w, "sum"), "sum")
+    check_exact(p.forward(to_dev(c.w), "max"), oracle.construction(m, c.D, c.Q, c.w, "max"), "max")
+    check_exact(p.forward(None, "count"), oracle.construction(m, c.D, c.Q, None, "count"), "count")
+    g = np.random.default_rng(10 + m).standard_normal(c.Q.shape[0]).astype(np.float32)
+    check_fp(p.backward(to_dev(g)), oracle.transposed_sum(m, c.D, c.Q, g.astype(np.float64)),
+             oracle.transposed_sum(m, c.D, c.Q, np.abs(g.astype(np.float64))), "grad")
+    from paper_2305_16751_amd import DomAggPlan
+    rng = np.random.default_rng(1450 + m)
+    sizes = [700, 0, 1100, 5]
+    Ds = [rng.integers(0, 50, size=(k, m), dtype=np.int32) for k in sizes]
+    Qs = [rng.integers(0, 50, size=(k + 3, m), dtype=np.int32) for k in sizes]
+    ws = [rng.integers(-9, 9, size=k).astype(np.int64) for k in sizes]
+    off = lambda xs: np.concatenate([[0], np.cumsum([x.shape[0] for x in xs])]).astype(np.int64)
+    pb = DomAggPlan(to_dev(np.concatenate(Ds)), to_dev(np.concatenate(Qs)), off(Ds), off(Qs))
+    want = np.concatenate([oracle.construction(m, Ds[k], Qs[k], ws[k], "sum") for k in range(len(sizes))])
+    check_exact(pb.forward(to_dev(np.concatenate(ws)), "sum"), want, "batched sum")
+
+
 def test_same_sign_fp32_weights_long_segments():
     """All-positive fp32 weights over segments that span hundreds of scan
     tiles: the error must stay within 2e-6 * sum |w| (compensated sums)."""
@@ -344,6 +372,46 @@ def test_small_batch_with_empty_instances(m):
         if Dk.shape[0]:
             want = oracle.transposed_sum(m, Dk, Qk, g[qoff[k]:qoff[k + 1]])
             np.testing.assert_allclose(gw[doff[k]:doff[k + 1]], want, rtol=1e-12, atol=1e-9)
+
+
+@pytest.mark.parametrize("m", [2, 3, 4])
+def test_batch_key_classes(m):
+    """A batch whose instances have different rank widths: the instance id
+    sits below the node fields of the record key, the sort reads the node
+    fields only (classes by key length, as for one instance), and each
+    (tuple, instance) run stays together.  Plan forward, backward and the
+    one-shot call (records carrying weights) per instance against the
+    oracle."""
+    from paper_2305_16751_amd import DomAggPlan, dom_agg_run
+    rng = np.random.default_rng(60 + m)
+    n = {2: 3000, 3: 800, 4: 250}[m]
+    sizes_d = [n, 17, 2 * n, 0, n // 2, 1]
+    sizes_q = [n + 1, 0, 2 * n - 5, 4, n // 2, 1]
+    alphas = [1 << 20, 6, 300, 50, 1 << 12, 9]
+    Ds = [rng.integers(0, a, size=(k, m), dtype=np.int32) for k, a in zip(sizes_d, alphas)]
+    Qs = [rng.integers(0, a, size=(k, m), dtype=np.int32) for k, a in zip(sizes_q, alphas)]
+    ws = [rng.integers(-500, 500, size=k).astype(np.int64) for k in sizes_d]
+    D, Q, w = np.concatenate(Ds), np.concatenate(Qs), np.concatenate(ws)
+    doff = np.concatenate([[0], np.cumsum(sizes_d)]).astype(np.int64)
+    qoff = np.concatenate([[0], np.cumsum(sizes_q)]).astype(np.int64)
+    p = DomAggPlan(to_dev(D), to_dev(Q), doff, qoff)
+    info = p.info()
+    assert info["sort_classes"] >= 2, info
+    assert sum(info["sort_class_records"]) == info["records"], info
+    want = np.concatenate([oracle.construction(m, Ds[k], Qs[k], ws[k], "sum") for k in range(len(sizes_d))])
+    check_exact(p.forward(to_dev(w), "sum"), want, "batched sum")
+    wmax = np.concatenate([oracle.construction(m, Ds[k], Qs[k], ws[k], "max") for k in range(len(sizes_d))])
+    check_exact(p.forward(to_dev(w), "max"), wmax, "batched max")
+    g = rng.standard_normal(Q.shape[0])
+    gw = p.backward(to_dev(g)).cpu().numpy()
+    gwant = np.concatenate([oracle.transposed_sum(m, Ds[k], Qs[k], g[qoff[k]:qoff[k + 1]])
+                            for k in range(len(sizes_d))])
+    np.testing.assert_allclose(gw, gwant, rtol=1e-12, atol=1e-9)
+    w32 = w.astype(np.int32)
+    got = dom_agg_run(to_dev(D), to_dev(Q), to_dev(w32), "sum", d_offsets=doff, q_offsets=qoff)
+    want32 = np.concatenate([oracle.construction(m, Ds[k], Qs[k], ws[k].astype(np.int32).astype(np.int64), "sum",
+                                                 weight_dtype=np.int32) for k in range(len(sizes_d))])
+    check_exact(got, want32, "batched one-shot sum i32")
 
 
 # ---------------------------------------------------------------------------
