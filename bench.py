@@ -193,17 +193,40 @@ def roofline_entry(kern, info, workload=None):
                            "read and written once per pass of its class), divided by the number of passes"}
 
 
-def cpu_baseline(n_sample=1 << 20):
+def _oracle_sample(args):
+    """One core's share of the CPU baseline: the oracle's construction on its
+    own seeded sample of the headline distribution (runs in a child process)."""
+    n, seed = args
     import oracle
     import workloads
-    c = workloads.f32_uniform(2, n_sample, workloads.BASE_SEED + 99, "sample")
+    c = workloads.f32_uniform(2, n, seed, "sample")
     w64 = c.w.astype(np.float64)
     t0 = time.perf_counter()
     oracle.construction(2, c.D, c.Q, w64, "sum")
-    dt = time.perf_counter() - t0
-    return {"value": round(2 * n_sample / dt, 1), "unit": "(|D|+|Q|)/s", "cores": 1, "kind": "oracle",
-            "sample": f"m=2, |D|=|Q|={n_sample}, float32 U[0,1) coordinates, float32 N(0,1) weights, "
-                      f"fp64 sequential construction (Sec. 4 + Sec. 5), {dt:.2f} s"}
+    return 2 * n, time.perf_counter() - t0
+
+
+def cpu_baseline(n_sample=1 << 20, cores=0):
+    """The oracle on the host's cores: one independent sample per core, all
+    at once (child processes, started fresh); the rate is the sum of the
+    per-core rates."""
+    import concurrent.futures
+    import multiprocessing
+    import workloads
+    if cores <= 0:
+        cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    ctx = multiprocessing.get_context("spawn")
+    jobs = [(n_sample, workloads.BASE_SEED + 99 + i) for i in range(cores)]
+    t0 = time.perf_counter()
+    with concurrent.futures.ProcessPoolExecutor(max_workers=cores, mp_context=ctx) as ex:
+        res = list(ex.map(_oracle_sample, jobs))
+    wall = time.perf_counter() - t0
+    rate = sum(p / dt for p, dt in res)
+    dts = [dt for _, dt in res]
+    return {"value": round(rate, 1), "unit": "(|D|+|Q|)/s", "cores": cores, "kind": "oracle",
+            "sample": f"m=2, |D|=|Q|={n_sample} per core ({cores} independent samples run at once, one process "
+                      f"each), float32 U[0,1) coordinates, float32 N(0,1) weights, fp64 sequential construction "
+                      f"(Sec. 4 + Sec. 5); per-core time {min(dts):.2f}-{max(dts):.2f} s, {wall:.1f} s wall"}
 
 
 def extra_plan_forward(case, steps):
@@ -373,7 +396,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-extras", action="store_true", help="only the headline workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 20)
+    ap.add_argument("--cpu-sample", type=int, default=1 << 20, help="points per side of each core's sample")
+    ap.add_argument("--cpu-cores", type=int, default=0, help="cores for the CPU baseline (0: up to 16 available)")
     ap.add_argument("--workload", choices=("f32_2d_16m", "f32_3d_1m"), default="f32_2d_16m",
                     help="the one-shot workload of the JSON line (profiling the m = 3 case; the metric's "
                          "workload is f32_2d_16m)")
@@ -384,6 +408,14 @@ def main():
         print(f"bench.py runs on one GPU only (the library has no multi-GPU path); got --gpus {args.gpus}",
               file=sys.stderr)
         sys.exit(2)
+
+    # the CPU baseline first: its worker processes start before this process
+    # touches the GPU
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on the host cores) ...")
+        cpu = cpu_baseline(args.cpu_sample, args.cpu_cores)
+        log(f"cpu baseline: {json.dumps(cpu)}")
 
     import torch
     import workloads
@@ -422,9 +454,8 @@ def main():
         "roofline": roofline_entry(kern, info, case.name),
     }
     extra = {"stages": stage_table(kern, args.steps, info, case.n, case.m - 1)}
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle on a sample) ...")
-        result["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+    if cpu is not None:
+        result["cpu_baseline"] = cpu
     if not args.no_extras:
         for name, fn in (("plan_forward", lambda: extra_plan_forward(case, 5)), ("m3", lambda: extra_m3(5)),
                          ("fwd_bwd", lambda: extra_fwd_bwd(5)), ("batched", lambda: extra_batched(3)),

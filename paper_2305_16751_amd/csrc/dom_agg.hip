@@ -274,18 +274,24 @@ bool compact_forced() {
     return e && e[0] == '1';
 }
 
-// DOM_AGG_PACK=0 keeps records as separate key and payload arrays (for
-// measurement); packing is on otherwise.
-// Whether the record sort's digit histograms come from a streaming pass over
-// the emitted records (else from inside the flat map): `dflt`, unless
-// DOM_AGG_SEP_HIST=0 or =1 says otherwise (for measurement).
-bool separate_histograms(bool dflt) {
-    const char *e = std::getenv("DOM_AGG_SEP_HIST");
-    if (e && e[0] == '0') return false;
-    if (e && e[0] == '1') return true;
-    return dflt;
+// Where the record sort's digit histograms come from: the rank CDFs, one
+// thread per tree node (m = 2, one instance); the points, in closed form; a
+// streaming pass over the emitted records; or the flat map's per-record
+// loop.  DOM_AGG_HIST=points / records / emit picks one of the last three
+// where it applies (for measurement); 0 when unset.
+enum class HistSource { kNodes, kPoints, kRecords, kEmit };
+
+int hist_source_override() {
+    const char *e = std::getenv("DOM_AGG_HIST");
+    if (!e || !e[0]) return 0;
+    if (!std::strcmp(e, "points")) return 1;
+    if (!std::strcmp(e, "records")) return 2;
+    if (!std::strcmp(e, "emit")) return 3;
+    fail(DOM_AGG_EINVAL, "DOM_AGG_HIST must be points, records or emit (got \"%s\")", e);
 }
 
+// DOM_AGG_PACK=0 keeps records as separate key and payload arrays (for
+// measurement); packing is on otherwise.
 bool packing_enabled() {
     static const bool on = [] {
         const char *e = std::getenv("DOM_AGG_PACK");
@@ -1130,17 +1136,27 @@ void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &ou
             default: f(std::integral_constant<int, 3>{}); break;
         }
     };
-    // m = 2 with classes: the digit histograms come from the rank CDFs, one
-    // thread per tree node, instead of one update per record in the flat map
-    // (not with <= on the first axis: the rank CDFs are of the unshifted ranks)
-    const bool node_hist = cls && P->cdf_d.p && P->m == 2 && !(P->le_mask & 1u);
-    // m >= 3 with one instance: from the emitted records, in a streaming pass
-    // after the flat map (measured faster there: 1.3 + 1.8 ms vs 3.6 ms for
-    // |D| = |Q| = 2^20 at m = 3); otherwise inside the flat map's per-record
-    // loop, where it hides behind the walk's latency (batched m = 2 and m = 4
-    // measured faster that way).  DOM_AGG_SEP_HIST=0 / 1 overrides.
-    const bool sep_hist = !node_hist && separate_histograms(P->nax >= 2 && !P->batched);
-    const bool emit_hist = !node_hist && !sep_hist;
+    // The digit histograms: m = 2 with classes from the rank CDFs per tree
+    // node (not with <= on the first axis: the CDFs are of the unshifted
+    // ranks); otherwise from the points in closed form, unless the instance
+    // id is among the sorted key bits (basic-variant batches) or there is no
+    // expanded axis: then inside the flat map's per-record loop.  (Per record,
+    // in the flat map or in a pass over the records, they cost 1.8 ms at
+    // m = 3, |D| = |Q| = 2^20.)
+    const bool can_points = P->nax >= 1 && P->inst_shift == 0;
+    HistSource hsrc = (cls && P->cdf_d.p && P->m == 2 && !(P->le_mask & 1u)) ? HistSource::kNodes
+                      : can_points                                            ? HistSource::kPoints
+                                                                              : HistSource::kEmit;
+    switch (hist_source_override()) {
+        case 1: if (can_points) hsrc = HistSource::kPoints; break;
+        case 2: hsrc = HistSource::kRecords; break;
+        case 3: hsrc = HistSource::kEmit; break;
+        default: break;
+    }
+    const bool node_hist = hsrc == HistSource::kNodes;
+    const bool point_hist = hsrc == HistSource::kPoints;
+    const bool sep_hist = hsrc == HistSource::kRecords;
+    const bool emit_hist = hsrc == HistSource::kEmit;
     // the flat map's workgroups: as many as are resident at once (each takes
     // a fixed share of the chunks)
     unsigned grid = 1;
@@ -1211,6 +1227,19 @@ void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &ou
         });
         a.hist_part = nullptr;  // the flat map skips its histograms
     }
+    if (point_hist) {
+        ngrid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(ceil_div(P->n, kBlock), 2048));
+        npart.alloc((size_t)ngrid * rows * kRadix * 4, s);
+        EmitArgs pa = a;
+        pa.hist_part = npart.as<uint32_t>();
+        per_nax([&](auto nax_c) {
+            constexpr int NAX = decltype(nax_c)::value;
+            if constexpr (NAX >= 1) {
+                launch("point_hist", s, [&] { point_hist_kernel<NAX><<<ngrid, kBlock, 0, s>>>(pa); });
+            }
+        });
+        a.hist_part = nullptr;
+    }
     if (cls) {
         // Records of each class per chunk (closed form over the points), their
         // exclusive sums over the chunks (each chunk's class offsets, so the
@@ -1277,7 +1306,7 @@ void build_records(Plan *P, hipStream_t s, HostStage *hs, bool probe, DevBuf &ou
                 emit_kernel<K, NAX, kBlock, EITEMS, false><<<grid, kBlock, 0, s>>>(a, ka, va, nullptr, nullptr);
         });
     });
-    if (node_hist) {
+    if (node_hist || point_hist) {
         reduce_hist(npart.as<uint32_t>(), (int)ngrid, rows, counts.as<uint32_t>(), bases.as<uint32_t>(), s);
     } else if (sep_hist) {
         RecHistArgs h{};

@@ -748,6 +748,112 @@ __global__ __launch_bounds__(256) void node_hist_kernel(const uint32_t *__restri
     if (rows) hist_flush(s_hist, a.hist_part, rows);
 }
 
+// Digit histograms from the points, for any m and batches whose instance id
+// is below the sorted bits.  A point's records are the tuples of its per-axis
+// node sets (Lemma 2's prefix sets, one node per selected level), and the
+// digit of pass p of a record's key is the OR of its nodes' slices in the
+// pass's bit window.  A node whose bits all lie below the window has a zero
+// slice, so per axis the nodes split into one zero group (counted) and the
+// nodes reaching into the window (taken one by one); every combination of
+// groups adds the product of the group sizes to its digit.  The combination
+// of zero groups only is summed over the wavefront first (it is the common
+// digit 0 of the high passes).  Work per point: the sum over classes and
+// passes of the combinations, far below one update per record and pass.
+
+// Every combination of the axes AX.. (the digit and multiplicity so far);
+// `picked`: an axis before AX took a reaching node.
+template <int AX, int NAX>
+__device__ __forceinline__ void point_hist_combos(uint32_t *row, const uint32_t *hi, const uint32_t *zero,
+                                                  const uint32_t *r, const uint32_t *L, const int *fs, int w0,
+                                                  uint32_t dmask, uint32_t digit, uint32_t mult, bool picked) {
+    if constexpr (AX == NAX) {
+        if (picked) atomicAdd(&row[digit], mult);
+    } else {
+        if (zero[AX]) point_hist_combos<AX + 1, NAX>(row, hi, zero, r, L, fs, w0, dmask, digit, mult * zero[AX], picked);
+        for (uint32_t m = hi[AX]; m; m &= m - 1u) {
+            const uint32_t b = (uint32_t)__ffs(m) - 1u;  // (lowest remaining) digit L-1-j of the rank string: level j
+            const uint32_t j = L[AX] - 1u - b;
+            const uint32_t node = (1u << j) | (j ? (r[AX] >> (L[AX] - j)) : 0u);
+            const uint32_t sl = (uint32_t)((((uint64_t)node) << fs[AX]) >> w0) & dmask;
+            point_hist_combos<AX + 1, NAX>(row, hi, zero, r, L, fs, w0, dmask, digit | sl, mult, true);
+        }
+    }
+}
+
+template <int NAX>
+__global__ __launch_bounds__(256) void point_hist_kernel(EmitArgs a) {
+    static_assert(NAX >= 1 && NAX <= 3, "");
+    __shared__ uint32_t s_hist[26 * kRadix];
+    const int rows = a.hist_rows;
+    for (int i = threadIdx.x; i < rows * kRadix; i += blockDim.x) s_hist[i] = 0;
+    __syncthreads();
+    const int lane = lane_id();
+    const int rb = a.rbits;
+    const uint32_t dmask = (1u << rb) - 1u;
+    const bool cls = a.ncls > 1;
+    const int ncls = cls ? a.ncls : 1;
+    int fs[NAX];
+#pragma unroll
+    for (int ax = 0; ax < NAX; ++ax) fs[ax] = a.field_shift[ax];
+    // every lane of a wavefront runs the same rounds (wavefront sums below)
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t k0 = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(uint64_t)(kWave - 1)); k0 < a.n;
+         k0 += stride) {
+        const uint64_t k = k0 + (uint64_t)lane;
+        bool valid = k < a.n;
+        uint32_t r[NAX], L[NAX], sel[NAX];
+        uint32_t ins = 0, pay = 0;
+        if (valid) {
+            pay = a.pay[k];
+            if (a.inst_s) ins = a.inst_s[k];
+            if (ins >= a.n_inst) valid = false;  // only if the sort were wrong
+        }
+        const bool isq = (pay & kQueryFlag) != 0u;
+#pragma unroll
+        for (int ax = 0; ax < NAX; ++ax) {
+            r[ax] = valid ? a.rs[(uint64_t)ax * a.n + k] : 0u;
+            L[ax] = valid ? (uint32_t)a.ltab[(uint64_t)ax * a.n_inst + ins] : 0u;
+            const uint32_t mask = L[ax] >= 32u ? 0xffffffffu : ((1u << L[ax]) - 1u);
+            sel[ax] = isq ? (r[ax] & mask) : (~r[ax] & mask);
+            if (sel[ax] == 0u) valid = false;  // no records
+        }
+        // the class masks are over the first axis's field width: aligned to
+        // this point's own width
+        const uint32_t align = L[0] <= (uint32_t)a.lmax0 ? (uint32_t)a.lmax0 - L[0] : 0u;
+        for (int c = 0; c < ncls; ++c) {
+            const uint32_t f0 = cls ? (sel[0] & (a.cls_mask[c] >> align)) : sel[0];
+            const bool vc = valid && f0 != 0u;
+            const int np = cls ? a.cls_passes[c] : a.passes;
+            uint32_t *rowp = s_hist + (cls ? a.cls_row0[c] : 0) * kRadix;
+            for (int p = 0; p < np; ++p, rowp += kRadix) {
+                const int w0 = a.sort_lo + rb * p;
+                uint32_t hi[NAX], zero[NAX];
+                uint32_t allz = vc ? 1u : 0u;
+#pragma unroll
+                for (int ax = 0; ax < NAX; ++ax) {
+                    const uint32_t sx = ax == 0 ? f0 : sel[ax];
+                    uint32_t h = 0;
+                    if (fs[ax] < w0 + rb) {
+                        const int kk = w0 > fs[ax] ? w0 - fs[ax] : 0;  // levels j >= kk reach past w0
+                        if (kk < (int)L[ax]) {
+                            const uint32_t nb = L[ax] - (uint32_t)kk;
+                            h = sx & (nb >= 32u ? 0xffffffffu : ((1u << nb) - 1u));
+                        }
+                    }
+                    hi[ax] = h;
+                    zero[ax] = (uint32_t)(__popc(sx) - __popc(h));
+                    allz *= zero[ax];
+                }
+                const uint32_t tot = wave_sum_scan_incl(allz);
+                if (lane == kWave - 1 && tot) atomicAdd(&rowp[0], tot);
+                if (vc) point_hist_combos<0, NAX>(rowp, hi, zero, r, L, fs, w0, dmask, 0u, 1u, false);
+            }
+        }
+    }
+    __syncthreads();
+    if (rows) hist_flush(s_hist, a.hist_part, rows);
+}
+
 // The flat map (Sec. 4 with Sec. 5).  Record o belongs to the point k with
 // off[k] <= o < off[k+1]; its index t = o - off[k] enumerates the product of
 // the point's per-axis prefix sets, last expanded axis fastest.  On axis a
