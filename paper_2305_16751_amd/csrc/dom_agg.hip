@@ -454,31 +454,44 @@ namespace {
 
 using Plan = dom_agg_plan_s;
 
-// small pinned host staging for the plan's size reads
-// (inside dom_agg_run_static: a fixed host buffer, read after a stream
-// synchronisation, instead of pinned memory)
+// Pinned host staging for the plan's size reads: one buffer per host thread,
+// grown on demand and kept for the life of the thread (a pinned allocation
+// costs tens of microseconds, and its release can wait for the device, both
+// while the device idles between a size read and the launches that follow
+// it).  Every use reads the buffer after a stream synchronisation and is
+// done with it before the next use.  Inside dom_agg_run_static: a fixed host
+// buffer instead.
 constexpr size_t kStaticHostBytes = 1u << 20;
 thread_local unsigned char t_static_host[kStaticHostBytes];
 
-struct HostStage {
+struct PinnedStage {
     void *p = nullptr;
     size_t bytes = 0;
-    ~HostStage() {
+    // (at thread exit; a thread's thread-local objects go before any static
+    // one, the runtime's included)
+    ~PinnedStage() {
         if (p) (void)hipHostFree(p);
     }
+};
+thread_local PinnedStage t_pinned;
+
+struct HostStage {
     void *get(size_t b) {
         if (t_arena) {
             if (b > kStaticHostBytes)
                 fail(DOM_AGG_ETOOBIG, "the call needs more than %zu bytes of host staging", kStaticHostBytes);
             return t_static_host;
         }
-        if (b > bytes) {
-            if (p) (void)hipHostFree(p);
-            p = nullptr;
-            HIPCHK(hipHostMalloc(&p, b, hipHostMallocDefault));
-            bytes = b;
+        if (b > t_pinned.bytes) {
+            if (t_pinned.p) (void)hipHostFree(t_pinned.p);
+            t_pinned.p = nullptr;
+            t_pinned.bytes = 0;
+            size_t nb = 64u << 10;
+            while (nb < b) nb <<= 1;
+            HIPCHK(hipHostMalloc(&t_pinned.p, nb, hipHostMallocDefault));
+            t_pinned.bytes = nb;
         }
-        return p;
+        return t_pinned.p;
     }
 };
 
@@ -490,11 +503,24 @@ unsigned grid_for(uint64_t n) {
 // once, at most `work`.
 template <class F>
 unsigned resident_grid(F kernel, uint64_t work) {
-    int dev = 0, cus = 0, per = 0;
+    int dev = 0;
     HIPCHK(hipGetDevice(&dev));
-    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kBlock, 0));
-    const uint64_t g = (uint64_t)std::max(per, 1) * (uint64_t)std::max(cus, 1);
+    // (the occupancy of a kernel on a device does not change: asked once)
+    static std::mutex mu;
+    static std::map<std::pair<const void *, int>, uint64_t> known;
+    uint64_t g;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = known.find({reinterpret_cast<const void *>(kernel), dev});
+        if (it == known.end()) {
+            int cus = 0, per = 0;
+            HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kBlock, 0));
+            it = known.emplace(std::make_pair(reinterpret_cast<const void *>(kernel), dev),
+                               (uint64_t)std::max(per, 1) * (uint64_t)std::max(cus, 1)).first;
+        }
+        g = it->second;
+    }
     return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(g, work));
 }
 

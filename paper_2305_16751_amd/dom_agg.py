@@ -13,6 +13,7 @@ everything else is the HIP library.
 from __future__ import annotations
 
 import ctypes
+import os
 
 import numpy as np
 import torch
@@ -57,7 +58,10 @@ def _lib():
     global _hook_installed
     lib = B.load()
     if not _hook_installed:
-        B.check(lib.dom_agg_set_allocator(_ALLOC_CB, _RELEASE_CB, None))
+        # DOM_AGG_TORCH_ALLOC=0 leaves the library on its own allocator (for
+        # measurement)
+        if os.environ.get("DOM_AGG_TORCH_ALLOC", "1") != "0":
+            B.check(lib.dom_agg_set_allocator(_ALLOC_CB, _RELEASE_CB, None))
         _hook_installed = True
     return lib
 
