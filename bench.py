@@ -132,6 +132,33 @@ def run_oneshot(case, steps, warmup, op="sum"):
     return T, kern, info, out
 
 
+def run_fwd_bwd(case, steps, warmup):
+    """Plan + forward + backward (fp32 sums; the gradient of sum(c * out))
+    per step, on one instance or a batch (case.d_offsets)."""
+    import torch
+    from paper_2305_16751_amd import DomAggPlan
+    d = torch.from_numpy(case.D).cuda()
+    q = torch.from_numpy(case.Q).cuda()
+    w = torch.from_numpy(case.w).cuda()
+    g = torch.from_numpy(case.c if getattr(case, "c", None) is not None else
+                         np.random.default_rng(5).standard_normal(case.Q.shape[0]).astype(np.float32)).cuda()
+    out = torch.empty(q.shape[0], device="cuda")
+    gw = torch.empty(d.shape[0], device="cuda")
+    offs = (case.d_offsets, case.q_offsets) if getattr(case, "d_offsets", None) is not None else (None, None)
+    info = {}
+
+    def step():
+        p = DomAggPlan(d, q, *offs)
+        p.forward(w, "sum", out=out)
+        p.backward(g, out=gw)
+        if not info:
+            info.update(p.info())
+        p.close()
+
+    T, kern = time_steps(step, steps, warmup)
+    return T, kern, info, out
+
+
 def run_plain(case, steps, warmup, op="sum"):
     import torch
     from paper_2305_16751_amd import DomAggPlan
@@ -398,9 +425,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 20, help="points per side of each core's sample")
     ap.add_argument("--cpu-cores", type=int, default=0, help="cores for the CPU baseline (0: up to 16 available)")
-    ap.add_argument("--workload", choices=("f32_2d_16m", "f32_3d_1m"), default="f32_2d_16m",
-                    help="the one-shot workload of the JSON line (profiling the m = 3 case; the metric's "
-                         "workload is f32_2d_16m)")
+    ap.add_argument("--workload", choices=("f32_2d_16m", "f32_3d_1m", "f32_2d_4m_grad", "batched_gmm4d"),
+                    default="f32_2d_16m",
+                    help="the workload of the JSON line (for profiling the others; the metric's workload is "
+                         "f32_2d_16m): one-shot calls for the first two, plan + forward + backward for the "
+                         "last two")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB elementwise copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -430,7 +459,11 @@ def main():
         del a, b
     case = getattr(workloads, args.workload)()
     log(f"headline: {case.name} m={case.m} |D|={case.D.shape[0]} |Q|={case.Q.shape[0]}")
-    T, kern, info, _ = run_oneshot(case, args.steps, args.warmup)
+    fwd_bwd = args.workload in ("f32_2d_4m_grad", "batched_gmm4d")
+    if fwd_bwd:
+        T, kern, info, _ = run_fwd_bwd(case, args.steps, args.warmup)
+    else:
+        T, kern, info, _ = run_oneshot(case, args.steps, args.warmup)
     value = case.n * args.steps / T
     log(f"headline: {T / args.steps * 1e3:.3f} ms/step, {value:.4g} (|D|+|Q|)/s, E={info['records']}")
     result = {
@@ -447,10 +480,14 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": case.name, "m": case.m, "n_data": int(case.D.shape[0]),
-                   "n_query": int(case.Q.shape[0]), "op": "sum", "coords": "float32 U[0,1)",
+                   "n_query": int(case.Q.shape[0]), "op": "sum",
+                   "coords": ("per-instance Gaussian mixtures" if case.name == "batched_gmm4d"
+                              else "float32 U[0,1)"),
                    "weights": "float32 N(0,1)", "records": info["records"], "key_bits": info["key_bits"],
                    "sort_passes": info["sort_passes"], "sort_classes": info["sort_classes"], "sort_tile": info["sort_tile"],
-                   "scan_tile": info["scan_tile"], "step": "dom_agg_run (plan + forward in one call)"},
+                   "scan_tile": info["scan_tile"],
+                   "step": ("dom_agg_plan + dom_agg_forward + dom_agg_backward" if fwd_bwd
+                            else "dom_agg_run (plan + forward in one call)")},
         "roofline": roofline_entry(kern, info, case.name),
     }
     extra = {"stages": stage_table(kern, args.steps, info, case.n, case.m - 1)}
