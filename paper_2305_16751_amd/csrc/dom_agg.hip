@@ -1481,7 +1481,11 @@ void regroup(const Plan *P, bool queries, const V *part, V *out, hipStream_t s) 
     const RegroupArgs ra = regroup_args(P, queries);
     const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(ceil_div(ra.nout, kBlock), 8192));
     if (!P->use_slots) {
-        launch("regroup", s, [&] { regroup_compact_kernel<V, OP><<<grid, kBlock, 0, s>>>(ra, P->nax, part, out); });
+        // (one wavefront per row)
+        const unsigned cgrid = (unsigned)std::max<uint64_t>(
+            1, std::min<uint64_t>(ceil_div(ra.nout, (uint64_t)(kBlock / kWave)), 8192));
+        launch("regroup", s,
+               [&] { regroup_compact_kernel<V, OP><<<cgrid, kBlock, 0, s>>>(ra, P->nax, part, out); });
         return;
     }
     auto go = [&](auto nax_c) {

@@ -1872,30 +1872,66 @@ __global__ __launch_bounds__(256) void regroup_kernel(RegroupArgs a, const Out *
 }
 
 // Compact mode: row o's partials are part[base, base + count) in level-tuple
-// order.  Each thread folds one row; a wavefront's rows hold consecutive
-// runs of the table.
+// order.  One wavefront folds one row: lane l takes partials l, l + 64, ...
+// of the run in order (the wavefront's loads are consecutive), then the
+// lanes' values are combined by a butterfly over lane distances 32, 16, ..,
+// 1.  The grouping depends only on the run's length, so results repeat bit
+// for bit; every F here is commutative (fp32 sums through F32c, whose
+// addition is symmetric), so both lanes of a butterfly pair hold the same
+// value.
+template <class A>
+__device__ __forceinline__ A lane_xor(A v, int mask) {
+    const int src = lane_id() ^ mask;
+    if constexpr (std::is_same<A, F32c>::value) {
+        return F32c{__uint_as_float(read_lane_u32(__float_as_uint(v.hi), src)),
+                    __uint_as_float(read_lane_u32(__float_as_uint(v.lo), src))};
+    } else if constexpr (sizeof(A) == 8) {
+        uint64_t u;
+        __builtin_memcpy(&u, &v, 8);
+        u = read_lane_u64(u, src);
+        A r;
+        __builtin_memcpy(&r, &u, 8);
+        return r;
+    } else {
+        static_assert(sizeof(A) == 4, "");
+        uint32_t u;
+        __builtin_memcpy(&u, &v, 4);
+        u = read_lane_u32(u, src);
+        A r;
+        __builtin_memcpy(&r, &u, 4);
+        return r;
+    }
+}
+
 template <class Out, int OP>
 __global__ __launch_bounds__(256) void regroup_compact_kernel(RegroupArgs a, int nax, const Out *__restrict__ part,
                                                               Out *__restrict__ out) {
     using A = typename AccumOf<Out, OP>::type;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t o = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; o < a.nout; o += stride) {
+    const int lane = lane_id();
+    const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x / kWave);
+    // every lane of a wavefront takes the same rows (the butterfly below)
+    for (uint64_t o = (uint64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; o < a.nout; o += nwaves) {
         const uint4 st = a.cstate[o];
         const uint32_t cnt = compact_count(st, nax);
-        A acc = Monoid<A, OP>::identity();
-        uint64_t i = st.x, end = (uint64_t)st.x + cnt;
+        uint64_t end = (uint64_t)st.x + cnt;
         if (end > a.cap) end = a.cap;  // (counts add up to the table size by construction)
-        // 4 partials per round, loaded before any is folded
-        for (; i + 4 <= end; i += 4) {
+        A acc = Monoid<A, OP>::identity();
+        uint64_t i = (uint64_t)st.x + (uint64_t)lane;
+        // 4 partials per lane and round, loaded before any is folded
+        for (; i + 3 * kWave < end; i += 4 * kWave) {
             Out v[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) v[u] = part[i + u];
+            for (int u = 0; u < 4; ++u) v[u] = part[i + (uint64_t)u * kWave];
 #pragma unroll
             for (int u = 0; u < 4; ++u) acc = Monoid<A, OP>::combine(acc, acc_from<A>(v[u]));
         }
-        for (; i < end; ++i) acc = Monoid<A, OP>::combine(acc, acc_from<A>(part[i]));
-        const uint64_t dst = a.inv ? (uint64_t)a.inv[o] : o;
-        if (dst < a.nout) out[dst] = acc_out<Out>(acc);  // (inv is a permutation of the rows)
+        for (; i < end; i += kWave) acc = Monoid<A, OP>::combine(acc, acc_from<A>(part[i]));
+#pragma unroll
+        for (int m = kWave / 2; m >= 1; m >>= 1) acc = Monoid<A, OP>::combine(acc, lane_xor(acc, m));
+        if (lane == 0) {
+            const uint64_t dst = a.inv ? (uint64_t)a.inv[o] : o;
+            if (dst < a.nout) out[dst] = acc_out<Out>(acc);  // (inv is a permutation of the rows)
+        }
     }
 }
 
