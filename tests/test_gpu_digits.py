@@ -55,6 +55,23 @@ def test_oneshot_at_width(width, m, n):
                 "one-shot sum i32")
 
 
+def test_batched_oneshot_at_width(width):
+    """Records carrying their weights in a batch: the query flag sits above
+    every digit read at either width, the instance id below them."""
+    from paper_2305_16751_amd import dom_agg_run
+    rng = np.random.default_rng(2550)
+    sizes = [3000, 1, 7000, 0, 250]
+    Ds = [rng.random((k, 2), dtype=np.float32) for k in sizes]
+    Qs = [rng.random((k + 11, 2), dtype=np.float32) for k in sizes]
+    ws = [rng.integers(-300, 300, size=k).astype(np.int32) for k in sizes]
+    off = lambda xs: np.concatenate([[0], np.cumsum([x.shape[0] for x in xs])]).astype(np.int64)
+    got = dom_agg_run(to_dev(np.concatenate(Ds)), to_dev(np.concatenate(Qs)), to_dev(np.concatenate(ws)), "sum",
+                      d_offsets=off(Ds), q_offsets=off(Qs), tune=False)
+    want = np.concatenate([oracle.construction(2, Ds[k], Qs[k], ws[k].astype(np.int64), "sum",
+                                               weight_dtype=np.int32) for k in range(len(sizes))])
+    check_exact(got, want, "batched one-shot sum i32")
+
+
 def test_batch_at_width(width):
     from paper_2305_16751_amd import DomAggPlan
     rng = np.random.default_rng(2500)
