@@ -463,14 +463,13 @@ struct CountProblemSigma {
     __device__ V combine(V a, V b) const { return a + b; }
     __device__ Raw load(uint64_t i) const { return Raw{keys[i], vals[i]}; }
     __device__ bool head(const Raw &, const Raw &) const { return false; }
-    __device__ V value(const Raw &, bool, const Raw &cur, uint64_t i) const {
+    // the point's state in last-axis order (while the tile is staged)
+    __device__ void pre(uint64_t i, const Raw &cur) const {
         const bool isq = (cur.v >> 63) != 0;
         const uint32_t r = (uint32_t)(cur.v >> 32) & 0x7fffffffu;
         const uint32_t payload = (uint32_t)cur.v;
         const uint32_t ins = inst(cur);
-        if (ins >= n_inst) return 0ull;  // only if the sort were wrong: no records
-        const uint32_t L = ltab[ins];
-        const uint32_t pc = (uint32_t)__popc(r);
+        if (ins >= n_inst) return;  // only if the sort were wrong
         rs[i] = r;
         if (isq) {
             pay[i] = kQueryFlag | (payload & ~kQueryFlag);
@@ -479,6 +478,14 @@ struct CountProblemSigma {
             if (INL) wv[i] = payload;
         }
         if (inst_s) inst_s[i] = ins;
+    }
+    __device__ V value(const Raw &, bool, const Raw &cur, uint64_t) const {
+        const bool isq = (cur.v >> 63) != 0;
+        const uint32_t r = (uint32_t)(cur.v >> 32) & 0x7fffffffu;
+        const uint32_t ins = inst(cur);
+        if (ins >= n_inst) return 0ull;  // only if the sort were wrong: no records
+        const uint32_t L = ltab[ins];
+        const uint32_t pc = (uint32_t)__popc(r);
         return isq ? pc : (L - pc);
     }
     __device__ void emit(uint64_t i, const Raw &, V, V excl, V incl, bool) const {

@@ -9,6 +9,11 @@
 //   bool head(const Raw &prev, const Raw &cur) const;   cur starts a segment
 //   V    value(const Raw &prev, bool has_prev, const Raw &cur, uint64_t i) const;
 //   void emit(uint64_t i, const Raw &cur, V v, V excl, V incl, bool last) const;
+// and optionally
+//   void pre(uint64_t i, const Raw &cur) const;   element-wise outputs that do
+//                                    not depend on the scan, written while
+//                                    the tile is staged (consecutive threads,
+//                                    consecutive elements: coalesced stores)
 // Element 0 always starts a segment; `last` says the element ends its segment.
 //
 // status holds 2 * tiles * (1 or 2) words, zero before the launch (tiles =
@@ -22,9 +27,19 @@
 // inside a segment walks back, stopping at the first inclusive status.
 #pragma once
 
+#include <type_traits>
+#include <utility>
+
 #include "device_common.hpp"
 
 namespace domagg {
+
+template <class P, class = void>
+struct HasPre : std::false_type {};
+template <class P>
+struct HasPre<P, std::void_t<decltype(std::declval<const P &>().pre(uint64_t(0),
+                                                                    std::declval<const typename P::Raw &>()))>>
+    : std::true_type {};
 
 template <class P, int BLOCK, int ITEMS>
 __global__ __launch_bounds__(BLOCK) void seg_scan_kernel(P p, uint64_t n,
@@ -67,7 +82,10 @@ __global__ __launch_bounds__(BLOCK) void seg_scan_kernel(P p, uint64_t n,
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
             const int li = j * BLOCK + tid;
-            if (base + li < n) s_raw[pidx(li)] = rr[j];
+            if (base + li < n) {
+                s_raw[pidx(li)] = rr[j];
+                if constexpr (HasPre<P>::value) p.pre(base + (uint64_t)li, rr[j]);
+            }
         }
     }
     if (tid == 0 && base > 0) s_pred = p.load(base - 1);
