@@ -188,10 +188,10 @@ dom_agg_status dom_agg_plan(dom_agg_plan_t *plan, int m, dom_agg_dtype coord_dty
  *   out      device, [n_query] of the output dtype, fully overwritten.
  *
  * Integer results and MAX are exact.  fp32/fp64 sums are exact up to
- * rounding order; that order is fixed (results repeat bit for bit) unless the
- * plan regroups with atomics (regroup_slots = 0 in dom_agg_plan_info, chosen
- * when the table of level-tuple slots would be large and sparse, e.g. m = 4
- * with wide ranks).
+ * rounding order, and that order is fixed for a plan (every fold, the
+ * regrouping included, runs in an order set by the records alone), so
+ * results repeat bit for bit; fp32 sums accumulate in a compensated pair of
+ * floats, so long runs keep their error to a few units in the last place.
  */
 dom_agg_status dom_agg_forward(dom_agg_plan_t plan, dom_agg_op op, dom_agg_dtype weight_dtype,
                                const void *weights, void *out, void *stream);
