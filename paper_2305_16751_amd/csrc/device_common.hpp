@@ -1,6 +1,6 @@
 // Device-side building blocks shared by the kernels: wave64 lane masks,
 // digit matching across a wavefront, agent-scope status words for decoupled
-// look-back, wavefront scans on DPP/permute, and atomic F into global memory.
+// look-back, wavefront scans on DPP/permute, and compensated fp32 sums.
 #pragma once
 
 #include <hip/hip_runtime.h>
