@@ -344,7 +344,7 @@ def test_sort_classes(m, n, alpha):
     check_exact(r.forward(to_dev(c.w), "sum"), oracle.construction(m, c.D, c.Q, c.w, "sum"), "recompute")
 
 
-@pytest.mark.parametrize("m", [2, 3])
+@pytest.mark.parametrize("m", [1, 2, 3])
 def test_small_batch_with_empty_instances(m):
     """Uneven instances, some without data or queries: per-instance results
     equal separate plans (internal numbering is per instance range)."""

@@ -68,25 +68,26 @@ def test_run_with_wide_keys():
     check_exact(_run(c, None, "count"), expected(3, c.D, c.Q, None, "count"), "wide count")
 
 
-def test_run_batched_with_empty_instances():
-    rng = np.random.default_rng(61)
+@pytest.mark.parametrize("m", [1, 2])
+def test_run_batched_with_empty_instances(m):
+    rng = np.random.default_rng(61 + m)
     sizes_d = [0, 5, 300, 1, 0, 700, 64, 2]
     sizes_q = [3, 0, 250, 0, 9, 650, 65, 1]
-    Ds = [rng.integers(0, 50 + 40 * k, size=(nd, 2), dtype=np.int32) for k, nd in enumerate(sizes_d)]
-    Qs = [rng.integers(0, 50 + 40 * k, size=(nq, 2), dtype=np.int32) for k, nq in enumerate(sizes_q)]
+    Ds = [rng.integers(0, 50 + 40 * k, size=(nd, m), dtype=np.int32) for k, nd in enumerate(sizes_d)]
+    Qs = [rng.integers(0, 50 + 40 * k, size=(nq, m), dtype=np.int32) for k, nq in enumerate(sizes_q)]
     ws = [rng.standard_normal(nd).astype(np.float32) for nd in sizes_d]
     doff = np.concatenate([[0], np.cumsum(sizes_d)]).astype(np.int64)
     qoff = np.concatenate([[0], np.cumsum(sizes_q)]).astype(np.int64)
-    c = workloads.Case("batch", 2, np.concatenate(Ds), np.concatenate(Qs), np.concatenate(ws))
+    c = workloads.Case("batch", m, np.concatenate(Ds), np.concatenate(Qs), np.concatenate(ws))
     out = _run(c, c.w, "sum", d_offsets=doff, q_offsets=qoff).cpu().numpy()
     mx = _run(c, c.w, "max", d_offsets=doff, q_offsets=qoff).cpu().numpy()
     for k in range(len(sizes_d)):
         if not sizes_q[k]:
             continue
         w64 = ws[k].astype(np.float64)
-        check_fp(torch.from_numpy(out[qoff[k]:qoff[k + 1]]), oracle.construction(2, Ds[k], Qs[k], w64, "sum"),
-                 oracle.construction(2, Ds[k], Qs[k], np.abs(w64), "sum"), f"instance {k}")
-        check_exact(torch.from_numpy(mx[qoff[k]:qoff[k + 1]]), oracle.construction(2, Ds[k], Qs[k], w64, "max"),
+        check_fp(torch.from_numpy(out[qoff[k]:qoff[k + 1]]), oracle.construction(m, Ds[k], Qs[k], w64, "sum"),
+                 oracle.construction(m, Ds[k], Qs[k], np.abs(w64), "sum"), f"instance {k}")
+        check_exact(torch.from_numpy(mx[qoff[k]:qoff[k + 1]]), oracle.construction(m, Ds[k], Qs[k], w64, "max"),
                     f"instance {k} max")
 
 
