@@ -72,6 +72,8 @@ def stage_table(kern, steps, info, n, nax, wbytes=4):
     model = {
         "flatmap_emit": E * rb + n * (8 + 4 + 4 * nax),
         "forward_scan": E * rb + ED * wbytes + EQ * wbytes,
+        # records that carry their weights: no weight gather
+        "forward_scan_inline": E * rb + EQ * wbytes,
         "backward_scan": E * rb + EQ * wbytes + ED * wbytes,
     }
     out = {}

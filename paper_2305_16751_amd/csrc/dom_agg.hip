@@ -1569,11 +1569,14 @@ void forward_run_pk(Plan *P, const void *kp, const uint32_t *vp, const void *w, 
     fp.q = part_dest<V>(P, true, P->nax == 0 ? res : P->part.as<V>());
     fp.d = PartDest<V>{};
     using FP = ForwardProblem<K, W, V, OP, INL, PK>;
+    // (a name of its own when the records carry the weights: no weight is
+    // gathered then, which the byte model of the timing report needs to know)
+    const char *name = INL ? "forward_scan_inline" : "forward_scan";
     if (P->tune.scan_items == 8 || sizeof(K) == 8)
-        scan_launch<FP, 8>("forward_scan", fp, (uint64_t)P->E, P->scan_status.as<uint64_t>(), P->scan_words,
+        scan_launch<FP, 8>(name, fp, (uint64_t)P->E, P->scan_status.as<uint64_t>(), P->scan_words,
                            P->scan_ticket.as<uint32_t>(), s);
     else
-        scan_launch<FP, 16>("forward_scan", fp, (uint64_t)P->E, P->scan_status.as<uint64_t>(), P->scan_words,
+        scan_launch<FP, 16>(name, fp, (uint64_t)P->E, P->scan_status.as<uint64_t>(), P->scan_words,
                             P->scan_ticket.as<uint32_t>(), s);
     if (P->nax > 0) regroup<V, OP>(P, true, P->part.as<V>(), res, s);
 }

@@ -72,3 +72,20 @@ def test_cpu_baseline_shape():
     assert cb["kind"] == "oracle" and cb["cores"] == 2 and cb["unit"] == "(|D|+|Q|)/s"
     assert cb["value"] > 0
     assert "per core" in cb["sample"]
+
+
+def test_stage_table_forward_scan_models():
+    """The forward scan gathers one weight per data record, unless the
+    records carry the weights (the one-shot call's own launch name); both
+    store one partial per query record."""
+    E, ED = 400_000_000, 160_000_000
+    info = {"records": E, "data_records": ED, "record_bytes": 8, "sort_classes": 1, "sort_passes": 2,
+            "sort_class_records": [E, 0, 0, 0]}
+    kern = {"forward_scan": (2.0, 1), "forward_scan_inline": (1.0, 1), "onesweep_records_packed_t8192": (4.0, 2)}
+    st = bench.stage_table(kern, 1, info, 100, 1)
+    gb = lambda k: st[k]["algorithmic_GB_per_launch"] * 1e9
+    assert gb("forward_scan") == pytest.approx(E * 8 + ED * 4 + (E - ED) * 4, rel=1e-4)
+    assert gb("forward_scan_inline") == pytest.approx(E * 8 + (E - ED) * 4, rel=1e-4)
+    # the sort: two passes over E packed records, each read and written once per pass
+    assert gb("onesweep_records_packed_t8192") == pytest.approx(2 * E * 8, rel=1e-4)
+    assert st["forward_scan_inline"]["GBps"] == pytest.approx((E * 8 + (E - ED) * 4) / 1e-3 / 1e9, rel=1e-4)
