@@ -258,12 +258,33 @@ def cpu_baseline(n_sample=1 << 20, cores=0):
                       f"(Sec. 4 + Sec. 5); per-core time {min(dts):.2f}-{max(dts):.2f} s, {wall:.1f} s wall"}
 
 
-def extra_plan_forward(case, steps):
+def extra_plan_forward(case, steps, reps=10):
     """The reusable-plan path on the headline workload: dom_agg_plan +
-    dom_agg_forward (payloads are indices, the scan gathers the weights)."""
+    dom_agg_forward (payloads are indices, the scan gathers the weights);
+    then dom_agg_forward alone on a kept plan, each call timed on its own
+    (median and minimum of reps calls after 3 warm-up calls)."""
+    import torch
+    from paper_2305_16751_amd import DomAggPlan
     T, kern, info, _ = run_plain(case, steps, 2)
+    d = torch.from_numpy(case.D).cuda()
+    q = torch.from_numpy(case.Q).cuda()
+    w = torch.from_numpy(case.w).cuda()
+    out = torch.empty(q.shape[0], dtype=torch.float32, device="cuda")
+    p = DomAggPlan(d, q)
+    for _ in range(3):
+        p.forward(w, "sum", out=out)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        p.forward(w, "sum", out=out)
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+    p.close()
     return {"workload": case.name, "value": round(case.n * steps / T, 1), "ms_per_step": round(T / steps * 1e3, 3),
             "step": "dom_agg_plan + dom_agg_forward",
+            "forward_kept_plan_ms": {"median": round(float(np.median(times)), 3), "min": round(min(times), 3),
+                                     "calls": reps},
             "stages": stage_table(kern, steps, info, case.n, case.m - 1)}
 
 
