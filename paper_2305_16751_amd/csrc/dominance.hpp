@@ -563,11 +563,17 @@ __device__ __forceinline__ uint32_t packed_prefix(uint64_t packed, int q) {
            (uint32_t)(x >> 48);
 }
 
+// Key-length class of a record key: the number of rb-bit digits that cover
+// its significant bits, less c0 (shorter keys share class 0).  The digit
+// count exceeds c0 + k exactly when the key has more than (c0 + k) * rb
+// significant bits, so the class is a sum of three comparisons (no division;
+// keys of a plan never need more than kMaxClasses classes).
+static_assert(kMaxClasses == 4, "three class thresholds");
 template <class K>
 __device__ __forceinline__ int key_class(K key, int c0, int rb) {
     const int bits = (int)(sizeof(K) * 8) - (sizeof(K) == 8 ? __clzll((long long)key) : __clz((int)key));
-    const int nominal = (bits + rb - 1) / rb;
-    return (nominal > c0 ? nominal : c0) - c0;
+    const int t0 = c0 * rb;
+    return (int)(bits > t0) + (int)(bits > t0 + rb) + (int)(bits > t0 + 2 * rb);
 }
 
 // chunk_k[c] = the point k with off[k] <= c * chunk < off[k+1].
@@ -1282,6 +1288,7 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(EmitArgs a, K *__restrict__
         const uint32_t nrec = (uint32_t)(o1 - o0);
         uint32_t nklo = 0, nkhi = 0;
         uint64_t tot = 0;  // the chunk's records per class (packed)
+        uint32_t cpre1 = 0, cpre2 = 0, cpre3 = 0;  // and in the classes below 1, 2 and 3
         // one copy of the chunk's code for cached and one for uncached points
         // (a run-time choice inside the loops below would make every wait
         // for LDS also wait for global memory)
@@ -1383,6 +1390,9 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(EmitArgs a, K *__restrict__
                     }
                 }
                 mine = block_excl_sum_packed<BLOCK>(expect, s_scan, &tot);
+                cpre1 = packed_prefix(tot, 1);
+                cpre2 = packed_prefix(tot, 2);
+                cpre3 = packed_prefix(tot, 3);
                 // destination of the chunk's first staged record of each class,
                 // minus its staging position
                 if (threadIdx.x < (unsigned)a.ncls) {
@@ -1408,7 +1418,8 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(EmitArgs a, K *__restrict__
                     uint32_t lp = threadIdx.x * ITEMS + j;
                     if constexpr (CLS) {
                         const int q = key_class((key & kmask) >> a.sort_lo, a.cls_c0, a.rbits);
-                        lp = packed_prefix(tot, q) + ((uint32_t)(mine >> (16 * q)) & 0xffffu);
+                        const uint32_t pre = q == 0 ? 0u : q == 1 ? cpre1 : q == 2 ? cpre2 : cpre3;
+                        lp = pre + ((uint32_t)(mine >> (16 * q)) & 0xffffu);
                         mine += 1ull << (16 * q);
                         seen += 1ull << (16 * q);
                     }
@@ -1461,10 +1472,8 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(EmitArgs a, K *__restrict__
                 uint64_t dst = o0 + i;
                 uint64_t *out = a.pk_a;
                 if constexpr (CLS) {
-                    int q = 0;
-#pragma unroll
-                    for (int t = 1; t < kMaxClasses; ++t)
-                        if (t < a.ncls && i >= packed_prefix(tot, t)) q = t;
+                    const int q = (int)(a.ncls > 1 && i >= cpre1) + (int)(a.ncls > 2 && i >= cpre2) +
+                                  (int)(a.ncls > 3 && i >= cpre3);
                     dst = s_cdst[q] + i;
                     if (!((cls_info >> (16 * q + 8)) & 1u)) out = a.pk_b;
                 }
@@ -1478,10 +1487,8 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(EmitArgs a, K *__restrict__
             }
         } else {
             for (uint32_t i = threadIdx.x; i < nrec; i += BLOCK) {
-                int q = 0;
-#pragma unroll
-                for (int t = 1; t < kMaxClasses; ++t)
-                    if (t < a.ncls && i >= packed_prefix(tot, t)) q = t;
+                const int q = (int)(a.ncls > 1 && i >= cpre1) + (int)(a.ncls > 2 && i >= cpre2) +
+                              (int)(a.ncls > 3 && i >= cpre3);
                 const uint64_t dst = s_cdst[q] + i;
                 if (dst >= a.E) continue;  // only if the class totals were wrong
                 if ((cls_info >> (16 * q + 8)) & 1u) {
