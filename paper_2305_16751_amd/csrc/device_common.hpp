@@ -27,17 +27,22 @@ __device__ __forceinline__ uint32_t count_below(uint64_t mask) {
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-// Lanes of the (fully active) wavefront holding the same BITS-bit digit.
+// Lanes of the (fully active) wavefront holding the same BITS-bit digit:
+// for every bit, the ballot of the lanes that have it set, complemented in
+// lanes where it is clear -- an XNOR with the lane's bit spread over a word
+// (written on 32-bit halves, so each bit costs a few plain bit operations
+// instead of a 64-bit select).
 template <int BITS>
 __device__ __forceinline__ uint64_t match_digit(uint32_t d) {
-    uint64_t m = ~0ull;
+    uint32_t lo = ~0u, hi = ~0u;
 #pragma unroll
     for (int b = 0; b < BITS; ++b) {
-        const bool bit = (d >> b) & 1u;
-        const uint64_t bal = __ballot(bit);
-        m &= bit ? bal : ~bal;
+        const uint32_t s = (uint32_t)((int32_t)(d << (31 - b)) >> 31);  // all ones where bit b is set
+        const uint64_t bal = __ballot(s != 0u);
+        lo &= ~((uint32_t)bal ^ s);
+        hi &= ~((uint32_t)(bal >> 32) ^ s);
     }
-    return m;
+    return ((uint64_t)hi << 32) | lo;
 }
 
 // ---------------------------------------------------------------------------
