@@ -1195,6 +1195,10 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(EmitArgs a, K *__restrict__
     __shared__ unsigned long long s_data;
     __shared__ uint64_t s_scan[BLOCK / kWave];
     __shared__ uint64_t s_cdst[kMaxClasses];  // destination of the chunk's first slot of each class, minus its run start
+    // packed records: where staged record i of class q goes (s_cptr[q][i]),
+    // for i below s_clim[q] (the rest would fall outside the record array)
+    __shared__ uint64_t *s_cptr[kMaxClasses];
+    __shared__ uint32_t s_clim[kMaxClasses];
     __shared__ uint32_t s_next[2];            // the block's next chunk's point range
     __shared__ uint16_t s_tfirst[BLOCK];      // cached chunks: the point holding each thread's first record (< kCap)
     const int rows = (HIST && a.hist_part) ? (CLS ? a.hist_rows : a.passes) : 0;
@@ -1397,7 +1401,14 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(EmitArgs a, K *__restrict__
                 // minus its staging position
                 if (threadIdx.x < (unsigned)a.ncls) {
                     const int q = threadIdx.x;
-                    s_cdst[q] = s_cls_base[q] + coff - packed_prefix(tot, q);
+                    const uint64_t cd = s_cls_base[q] + coff - packed_prefix(tot, q);
+                    s_cdst[q] = cd;
+                    if (a.pk_a) {
+                        uint64_t *const out = ((cls_info >> (16 * q + 8)) & 1u) ? a.pk_a : a.pk_b;
+                        const bool in = cd < a.E;  // (always, unless the class totals were wrong)
+                        s_cptr[q] = in ? out + cd : out;
+                        s_clim[q] = in ? (uint32_t)((a.E - cd) < (uint64_t)CHUNK ? (a.E - cd) : (uint64_t)CHUNK) : 0u;
+                    }
                 }
             }
 
@@ -1467,19 +1478,28 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(EmitArgs a, K *__restrict__
         // the next chunk's points, loaded while this chunk's records are stored
         if (cn < nchunks) prefetch(cn, nklo, nkhi);
         if (a.pk_a) {
-            // packed records: one 64-bit word per record
-            for (uint32_t i = threadIdx.x; i < nrec; i += BLOCK) {
-                uint64_t dst = o0 + i;
-                uint64_t *out = a.pk_a;
-                if constexpr (CLS) {
-                    const int q = (int)(a.ncls > 1 && i >= cpre1) + (int)(a.ncls > 2 && i >= cpre2) +
-                                  (int)(a.ncls > 3 && i >= cpre3);
-                    dst = s_cdst[q] + i;
-                    if (!((cls_info >> (16 * q + 8)) & 1u)) out = a.pk_b;
+            // packed records: one 64-bit word per record (the payload kind is
+            // uniform, so each kind gets a loop of its own)
+            auto store_packed = [&](auto labels_c) {
+                constexpr bool LABELS = decltype(labels_c)::value;
+                for (uint32_t i = threadIdx.x; i < nrec; i += BLOCK) {
+                    const uint64_t w = pack_record(s_keys[i], s_pay[i], a.pk_shift, LABELS);
+                    if constexpr (CLS) {
+                        const int q = (int)(a.ncls > 1 && i >= cpre1) + (int)(a.ncls > 2 && i >= cpre2) +
+                                      (int)(a.ncls > 3 && i >= cpre3);
+                        if (i >= s_clim[q]) continue;  // only if the class totals were wrong
+                        // (a pointer read from LDS: taken as global memory, so the
+                        // store is a global one and not a flat one)
+                        using GPtr = __attribute__((address_space(1))) uint64_t *;
+                        ((GPtr)s_cptr[q])[i] = w;
+                    } else {
+                        if (o0 + i >= a.E) continue;
+                        a.pk_a[o0 + i] = w;
+                    }
                 }
-                if (dst >= a.E) continue;  // only if the class totals were wrong
-                out[dst] = pack_record(s_keys[i], s_pay[i], a.pk_shift, a.pk_labels);
-            }
+            };
+            if (a.pk_labels) store_packed(std::true_type{});
+            else store_packed(std::false_type{});
         } else if constexpr (!CLS) {
             for (uint32_t i = threadIdx.x; i < nrec; i += BLOCK) {
                 keys_a[o0 + i] = s_keys[i];
