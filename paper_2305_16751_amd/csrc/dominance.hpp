@@ -607,6 +607,7 @@ struct PointWalk {
     uint32_t r[3], L[3], full[3], rem[3];
     uint32_t payload, inst;  // payload: what the point's records carry
     bool isq;
+    uint64_t kbase;  // the key bits every record of the point shares: instance and query flag
 
     // lsingle: the levels of every axis (8 bits each) when there is one
     // instance, else ~0u (then they are read per point)
@@ -615,6 +616,8 @@ struct PointWalk {
         isq = (pay & kQueryFlag) != 0u;
         payload = a.flag_shift < 0 ? pay : (isq ? (pay & ~kQueryFlag) : wbits);
         inst = ins;
+        kbase = (a.inst_s ? (uint64_t)ins << a.inst_shift : 0ull) |
+                ((a.flag_shift >= 0 && isq) ? 1ull << a.flag_shift : 0ull);
 #pragma unroll
         for (int ax = 0; ax < NAX; ++ax) {
             r[ax] = ranks[ax];
@@ -659,14 +662,14 @@ struct PointWalk {
         }
     }
     template <class K>
-    __device__ K key(int inst_shift, bool with_inst, const int *field_shift, int flag_shift) const {
-        K key = with_inst ? ((K)inst << inst_shift) : K(0);
-        if (flag_shift >= 0 && isq) key |= K(1) << flag_shift;
+    __device__ K key(const int *field_shift) const {
+        K key = (K)kbase;
 #pragma unroll
         for (int ax = 0; ax < NAX; ++ax) {
             const uint32_t top = 31u - (uint32_t)__clz(rem[ax]);  // highest remaining digit
             const uint32_t j = L[ax] - 1u - top;                 // its position from the top
-            const uint32_t node = (1u << j) | (j ? (r[ax] >> (L[ax] - j)) : 0u);
+            // (a 64-bit shift: the prefix of length 0 shifts by L, which may be 32)
+            const uint32_t node = (1u << j) | (uint32_t)((uint64_t)r[ax] >> (L[ax] - j));
             key |= (K)node << field_shift[ax];
         }
         return key;
@@ -1425,11 +1428,14 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(EmitArgs a, K *__restrict__
                 const bool valid = r0 + j < o1;
                 K key = 0;
                 if (valid) {
-                    key = pw.template key<K>(a.inst_shift, with_inst, a.field_shift, a.flag_shift);
+                    key = pw.template key<K>(a.field_shift);
                     uint32_t lp = threadIdx.x * ITEMS + j;
                     if constexpr (CLS) {
                         const int q = key_class((key & kmask) >> a.sort_lo, a.cls_c0, a.rbits);
-                        const uint32_t pre = q == 0 ? 0u : q == 1 ? cpre1 : q == 2 ? cpre2 : cpre3;
+                        // (the prefix of class q as a sum of masked steps: selects, no branches)
+                        const uint32_t pre = (cpre1 & (0u - (uint32_t)(q > 0))) +
+                                             ((cpre2 - cpre1) & (0u - (uint32_t)(q > 1))) +
+                                             ((cpre3 - cpre2) & (0u - (uint32_t)(q > 2)));
                         lp = pre + ((uint32_t)(mine >> (16 * q)) & 0xffffu);
                         mine += 1ull << (16 * q);
                         seen += 1ull << (16 * q);
