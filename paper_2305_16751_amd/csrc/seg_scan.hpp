@@ -15,6 +15,9 @@
 //                                    the tile is staged (consecutive threads,
 //                                    consecutive elements: coalesced stores)
 // Element 0 always starts a segment; `last` says the element ends its segment.
+// combine must be associative; with an integral V it must also be exact, as
+// integer sums and maxima are: the look-back then folds tile aggregates in a
+// tree rather than strictly left to right.
 //
 // status holds 2 * tiles * (1 or 2) words, zero before the launch (tiles =
 // ceil(n / (BLOCK * ITEMS))).
@@ -257,7 +260,21 @@ __global__ __launch_bounds__(BLOCK) void seg_scan_kernel(P p, uint64_t n,
                 for (int k = 0; k < kDepth; ++k) {
                     const int64_t left = (int64_t)tile - (w0 + kWave * k);
                     const int cnt = left <= 0 ? 0 : (left < kWave ? (int)left : kWave);
-                    for (int l = 0; l < cnt; ++l) carry = p.combine(carry, read_uniform_lane(av[k], l));
+                    if constexpr (std::is_integral<V>::value) {
+                        // Integer values: every grouping gives the left fold's
+                        // result exactly, so the wavefront folds the 64
+                        // aggregates as a tree (blocks of 2, 4, ... lanes, in
+                        // tile order) instead of one after another.
+                        V x = lane < cnt ? av[k] : p.identity();
+#pragma unroll
+                        for (int off = 1; off < kWave; off <<= 1) {
+                            const V y = read_lane(x, lane ^ off);
+                            x = (lane & off) ? p.combine(y, x) : p.combine(x, y);
+                        }
+                        carry = p.combine(carry, x);
+                    } else {
+                        for (int l = 0; l < cnt; ++l) carry = p.combine(carry, read_uniform_lane(av[k], l));
+                    }
                 }
             }
             if (!rf && lane == 0) publish_status(status, tile, kFlagInclusive, p.combine(carry, run));
