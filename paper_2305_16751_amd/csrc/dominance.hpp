@@ -1664,7 +1664,10 @@ __device__ __forceinline__ Out acc_out(A a) {
 // packed weight payloads (records that carry weights) take all 32 bits.
 // PK (the layout) and LABELS (the payload kind) are compile-time choices:
 // a run-time branch inside the scans' load loops made the compiler wait for
-// every load before the next one was issued.
+// every load before the next one was issued.  The records are read once per
+// scan, so the loads are non-temporal: they leave L2 to the lines of the
+// scattered partial stores, whose bytes combine there (forward scan at
+// f32_2d_16m 2.69 -> 2.65 ms).
 template <class K, bool PK>
 struct RecSrc {
     const K *keys;
@@ -1674,7 +1677,7 @@ struct RecSrc {
     template <bool LABELS = true>
     __device__ __forceinline__ void get(uint64_t i, K &k, uint32_t &pay) const {
         if constexpr (PK) {
-            const uint64_t w = packed[i];
+            const uint64_t w = __builtin_nontemporal_load(&packed[i]);
             k = (K)(w >> pay_bits);
             if constexpr (LABELS) {
                 const uint32_t row = (uint32_t)w & ((1u << (pay_bits - 1)) - 1u);
@@ -1683,8 +1686,8 @@ struct RecSrc {
                 pay = (uint32_t)w;
             }
         } else {
-            k = keys[i];
-            pay = vals[i];
+            k = __builtin_nontemporal_load(&keys[i]);
+            pay = __builtin_nontemporal_load(&vals[i]);
         }
     }
 };
