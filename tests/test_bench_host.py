@@ -89,3 +89,18 @@ def test_stage_table_forward_scan_models():
     # the sort: two passes over E packed records, each read and written once per pass
     assert gb("onesweep_records_packed_t8192") == pytest.approx(2 * E * 8, rel=1e-4)
     assert st["forward_scan_inline"]["GBps"] == pytest.approx((E * 8 + (E - ED) * 4) / 1e-3 / 1e9, rel=1e-4)
+
+
+def test_stage_model_names_are_launch_names():
+    """Every stage the byte model prices is a name the library times its
+    launches under (a renamed launch would silently drop its rate), and so
+    is every record-sort name the roofline figure can be quoted on."""
+    src = open(os.path.join(ROOT, "paper_2305_16751_amd", "csrc", "dom_agg.hip")).read()
+    info = {"records": 10, "data_records": 4, "record_bytes": 8, "sort_classes": 1, "sort_passes": 1,
+            "sort_class_records": [10, 0, 0, 0]}
+    for name in ("flatmap_emit", "forward_scan", "forward_scan_inline", "backward_scan"):
+        assert bench.stage_table({name: (1.0, 1)}, 1, info, 1, 1)[name].get("algorithmic_GB_per_launch") is not None
+        assert f'"{name}"' in src, name
+    for name in ("onesweep_records_packed_t8192", "onesweep_records_packed_t8192_d7", "onesweep_records_u64_t4096",
+                 "onesweep_records_u32_t8192"):
+        assert f'"{name}"' in src, name
